@@ -1,0 +1,32 @@
+"""Memoized oracle products shared by tests (all computed by oracle/ only)."""
+import functools
+import math
+
+from oracle import core, gaunt
+
+
+@functools.lru_cache(maxsize=None)
+def coo(L):
+    return gaunt.coo(L)
+
+
+@functools.lru_cache(maxsize=None)
+def core_zeroed(K, L, gamma, b0=1.0 / (4 * math.pi)):
+    T = coo(L)
+    return core.zero_invariants(core.core_exact(K, L, gamma, b0=b0, table=T), T["channels"])
+
+
+@functools.lru_cache(maxsize=None)
+def core_raw(K, L, gamma, b0=1.0 / (4 * math.pi)):
+    return core.core_exact(K, L, gamma, b0=b0, table=coo(L))
+
+
+def golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = []
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append(line.split())
+    return rows
