@@ -1,0 +1,130 @@
+/*
+ * wefq: Wigner-Eckart factorized spectral Boltzmann collision operator
+ * on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operator (Sections 2.1-2.3 of the paper): for a distribution
+ * f = M~ sum_alpha c_alpha phi_alpha in the Laguerre x real-spherical-harmonic
+ * basis alpha = (k, l, m), the Galerkin collision term is
+ *     Q_alpha1(c) = sum_{alpha2, alpha3} C_{alpha1 alpha2 alpha3} c_alpha2 c_alpha3,
+ * with C the 8-D weak form of Q(f, f) for the kernel B = b0 u^gamma.  Via the
+ * Wigner-Eckart factorization (eq. wigner-eckart-factorization, Section 4.1)
+ * C = R^{(l1 l2 l3)}_{k1 k2 k3} g(q1, q2, q3), where g is the real Gaunt
+ * weight and R the dense radial kinematic core.
+ *
+ * Conventions shared by every entry point:
+ *   q = l*l + l + m (0-based), flat mode index n = q * (Kmax+1) + k,
+ *   N = (Kmax+1)(Lmax+1)^2 modes per cell (box truncation, Section 4.6).
+ *   Coefficient batches are row-major [B][ld] with the N modes of one cell
+ *   contiguous.  phi_000 = 1, so the unit Maxwellian is c = e_0.
+ *
+ * Error behaviour: every call returns a wefq_status and never aborts; no C++
+ * exception crosses the ABI.  wefq_last_error() returns a thread-local message
+ * describing the last non-OK status of the calling thread.  Device faults of
+ * asynchronous launches surface at the caller's next synchronization.
+ */
+#ifndef WEFQ_H
+#define WEFQ_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wefq_core* wefq_handle;
+typedef struct wefq_plan_s* wefq_plan;
+
+typedef enum {
+  WEFQ_OK = 0,
+  WEFQ_EINVAL = 1,        /* bad argument (null pointer, size, layout, precision) */
+  WEFQ_ENOMEM = 2,        /* device or host allocation failed */
+  WEFQ_EHIP = 3,          /* HIP runtime error */
+  WEFQ_EUNSUPPORTED = 4,  /* truncation or precision not supported by this build */
+  WEFQ_EBUDGET = 5        /* request does not fit the given memory budget */
+} wefq_status;
+
+typedef enum {
+  WEFQ_MAXWELL = 0,       /* gamma = 0  (Maxwell molecules) */
+  WEFQ_HARD_SPHERE = 1,   /* gamma = 1 */
+  WEFQ_VHS = 2            /* variable hard sphere, gamma from the descriptor */
+} wefq_model;
+
+typedef enum {
+  WEFQ_FP64 = 1,          /* plain FP64 contraction; f and Q are double */
+  WEFQ_FP32 = 2,          /* FP32 angular coupling + FP32 MFMA radial contraction; float */
+  WEFQ_BF16X3 = 4         /* FP32 angular coupling + split hi/lo BF16 MFMA (3 products,
+                             FP32 accumulation); f and Q are float */
+} wefq_precision;
+
+/* Descriptor of a radial core.  The collision kernel is B(u, cos chi) = b0 u^gamma
+ * (isotropic, Grad cut-off; Section 2.1).  b0 <= 0 selects b0 = 1/(4 pi), for which
+ * int B du' = u^gamma.  precisions is a bitmask of wefq_precision values to prepare. */
+typedef struct {
+  int32_t model;
+  double gamma;           /* used when model == WEFQ_VHS; must be in [0, 2] */
+  double b0;
+  int32_t Kmax;           /* 0 <= Kmax <= 16 */
+  int32_t Lmax;           /* 0 <= Lmax <= 16 */
+  uint32_t precisions;
+  int32_t device;         /* HIP device ordinal */
+} wefq_core_desc;
+
+typedef struct {
+  int64_t N, NK, NQ;      /* modes, radial and angular sizes */
+  int64_t N_T, N_G, N_S;  /* channels, COO rows, (channel, q1) slices (Section 4.7) */
+  int64_t N_T_merged, N_G_merged, N_S_merged; /* after pairing (q1,q2,q3) with (q1,q3,q2) */
+  int64_t quad_nodes;     /* quadrature nodes used to integrate the core */
+  int64_t device_bytes;   /* device memory held by the handle */
+  double flop_alg_per_cell; /* 2 NK^2 N_G + 2 NK^3 N_S (Section 4.7, angular-first count) */
+  double gamma, b0;
+} wefq_core_info;
+
+/* Build the radial core R (Sections 3.2-3.3, 4.3-4.4) on the GPU in FP64 and the
+ * routing tables (Sections 4.1-4.2).  R is integrated by an exact Gauss rule in
+ * centre-of-mass / relative-velocity variables, then its collision-invariant rows
+ * (mass, momentum, energy) and the detailed-balance vector are set to exactly 0
+ * (Section 4.4).  Synchronous: returns when the handle is ready.  stream may be
+ * NULL (the default stream).  On success *out owns all device memory of the core;
+ * release it with wefq_destroy.  The handle is read-only afterwards and may be
+ * used concurrently from several streams. */
+wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handle* out);
+
+wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info);
+
+/* Copy the zeroed FP64 core to host memory: R[c][k1][k2][k3], c in the paper's
+ * channel order (l1 outer, l2, l3 inner), count = N_T * NK^3 doubles. */
+wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count);
+
+/* Q = Q(f, f) for B independent cells (eq. full_discrete_sum, Section 4.5).
+ * f and Q are device pointers, row-major [B][ld_f] / [B][ld_q], ld >= N,
+ * double for WEFQ_FP64 and float otherwise, 16-byte aligned, not aliasing.
+ * Q is overwritten (not accumulated).  B == 0 is a no-op.  Asynchronous on
+ * stream; allocates nothing.  The mass, momentum and energy rows of Q are
+ * exactly 0 for every precision.  NaN/Inf in f propagate elsewhere. */
+wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* Q,
+                         int64_t B, int64_t ld_f, int64_t ld_q, void* stream);
+
+/* FP64 check of the five collision-invariant rows (Section 4.4) of a computed Q:
+ * *max_abs = max over cells of |Q| on those rows (exactly 0 when conservation
+ * holds).  Synchronizes stream. */
+wefq_status wefq_check_conservation(wefq_handle h, int32_t precision, const void* Q,
+                                    int64_t B, int64_t ld_q, double* max_abs, void* stream);
+
+wefq_status wefq_destroy(wefq_handle h);
+
+const char* wefq_last_error(void);
+
+/* ---- host-only helpers (no device needed), used to test the host tables ---- */
+
+/* Real-Gaunt COO table (Table 1 order: q3 slowest, q1 fastest, 0-based).  Call
+ * with null arrays to get *count; then again with arrays of *count entries. */
+wefq_status wefq_host_coo(int32_t Lmax, int64_t* count, int32_t* q1, int32_t* q2,
+                          int32_t* q3, int32_t* channel, double* g);
+
+/* Gauss rule: kind 0 Gauss-Legendre on [-1,1]; kind 1 generalized Gauss-Laguerre
+ * with weight x^alpha e^{-x}.  x and w have n entries. */
+wefq_status wefq_host_gauss(int32_t kind, int32_t n, double alpha, double* x, double* w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WEFQ_H */

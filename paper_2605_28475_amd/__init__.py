@@ -1,0 +1,127 @@
+"""wefq: Wigner-Eckart factorized Boltzmann collision operator on MI355X.
+
+Thin Python binding over libwefq.so (C ABI in include/wefq.h).  PyTorch is used
+only to hold device memory and to name the HIP stream; every step of the
+computation runs in the library's HIP kernels.  There is no CPU fallback: the
+calls raise if the HIP library is missing.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import BF16X3, FP32, FP64, HARD_SPHERE, MAXWELL, VHS, WefqError
+
+MODELS = {"maxwell": MAXWELL, "mm": MAXWELL, "hard_sphere": HARD_SPHERE, "hs": HARD_SPHERE, "vhs": VHS}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+
+def num_modes(K, L):
+    return (K + 1) * (L + 1) ** 2
+
+
+def _stream_ptr(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Core:
+    """A built radial core (wefq_build_core) resident on one GPU."""
+
+    def __init__(self, model, K, L, gamma=None, b0=0.0, precisions=("fp64", "fp32", "bf16x3"),
+                 device=0, stream=None):
+        m = MODELS[model] if isinstance(model, str) else int(model)
+        if gamma is None:
+            gamma = {MAXWELL: 0.0, HARD_SPHERE: 1.0}.get(m, 0.5)
+        mask = 0
+        for p in precisions:
+            mask |= PRECISIONS[p] if isinstance(p, str) else int(p)
+        desc = _lib.CoreDesc(m, float(gamma), float(b0), int(K), int(L), mask, int(device))
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().wefq_build_core(ctypes.byref(desc), _stream_ptr(stream, device), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.K, self.L = int(K), int(L)
+        self.model, self.gamma = m, float(gamma)
+        info = _lib.CoreInfo()
+        _lib.check(_lib.lib().wefq_core_info_get(h, ctypes.byref(info)))
+        self.info = {name: getattr(info, name) for name, _ in _lib.CoreInfo._fields_}
+        self.N = int(info.N)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def download_R(self):
+        NK = self.K + 1
+        out = np.empty((self.info["N_T"], NK, NK, NK), dtype=np.float64)
+        _lib.check(_lib.lib().wefq_core_download_R(self._h, out.ctypes.data_as(ctypes.c_void_p), out.size))
+        return out
+
+    def _prec(self, f, precision):
+        import torch
+        if precision is None:
+            return FP64 if f.dtype == torch.float64 else FP32
+        return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+    def apply_Q(self, f, out=None, precision=None, stream=None):
+        """Q(f, f) for a [B, N] (or [N]) device tensor; returns a new tensor unless out is given."""
+        import torch
+        squeeze = f.dim() == 1
+        f2 = f.unsqueeze(0) if squeeze else f
+        prec = self._prec(f2, precision)
+        want = torch.float64 if prec == FP64 else torch.float32
+        if f2.dtype != want or f2.device.type != "cuda" or f2.stride(-1) != 1:
+            raise ValueError(f"f must be a CUDA {want} tensor with unit stride in the last dimension")
+        B = f2.shape[0]
+        if out is None:
+            out = torch.empty((B, f2.shape[1]), dtype=want, device=f2.device)
+        _lib.check(_lib.lib().wefq_apply_Q(self._h, prec, ctypes.c_void_p(f2.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), B, f2.stride(0) if B > 1 else f2.shape[1],
+                                           out.stride(0) if B > 1 else out.shape[1],
+                                           _stream_ptr(stream, f2.device)))
+        return out[0] if squeeze else out
+
+    def check_conservation(self, Q, precision=None, stream=None):
+        import torch
+        Q2 = Q.unsqueeze(0) if Q.dim() == 1 else Q
+        prec = self._prec(Q2, precision)
+        res = ctypes.c_double()
+        _lib.check(_lib.lib().wefq_check_conservation(self._h, prec, ctypes.c_void_p(Q2.data_ptr()), Q2.shape[0],
+                                                      Q2.stride(0) if Q2.shape[0] > 1 else Q2.shape[1],
+                                                      ctypes.byref(res), _stream_ptr(stream, Q2.device)))
+        return res.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.check(_lib.lib().wefq_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def host_coo(L):
+    """Real-Gaunt COO table from the library's host code (no GPU needed)."""
+    n = ctypes.c_int64()
+    _lib.check(_lib.lib().wefq_host_coo(L, ctypes.byref(n), None, None, None, None, None))
+    cnt = n.value
+    arrs = {k: np.empty(cnt, dtype=np.int32) for k in ("q1", "q2", "q3", "c")}
+    g = np.empty(cnt, dtype=np.float64)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _lib.check(_lib.lib().wefq_host_coo(L, ctypes.byref(n), ptr(arrs["q1"]), ptr(arrs["q2"]), ptr(arrs["q3"]),
+                                        ptr(arrs["c"]), ptr(g)))
+    arrs["g"] = g
+    return arrs
+
+
+def host_gauss(kind, n, alpha=0.0):
+    x = np.empty(n); w = np.empty(n)
+    _lib.check(_lib.lib().wefq_host_gauss(kind, n, alpha, x.ctypes.data_as(ctypes.c_void_p),
+                                          w.ctypes.data_as(ctypes.c_void_p)))
+    return x, w

@@ -1,0 +1,354 @@
+// Contraction kernels for Q(f, f) (Section 4.5) and the FP64 conservation check.
+//
+// apply_fp64_kernel   the plain FP64 comparator: the paper's naive contraction
+//                     (eq. full_discrete_sum as written), one thread per output
+//                     (cell, q1, k1), looping over the COO rows of q1 and k2, k3.
+// apply_mfma_kernel   angular-first contraction (Section 4.5.4) re-laid for CDNA4:
+//   * a workgroup owns a tile of 16 cells (8 when f does not fit in LDS; then
+//     the 16 MFMA columns are 8 cells x 2 output states) and stages their
+//     coefficients in LDS as fs[n][cell];
+//   * the COO rows (q1,q2,q3) and (q1,q3,q2) are merged (exact for Q(f,f)), so
+//     channel (l1,l2,l3) with l2 < l3 carries R^{(l1l2l3)}_{k1k2k3} + R^{(l1l3l2)}_{k1k3k2};
+//   * per slice (channel, q1) the intermediate Phi^{(c,q1)}_{k2k3} =
+//     sum_z g_z f_{k2,q2z} f_{k3,q3z} (angular coupling, FP32 VALU) is built by
+//     wave-uniform integer-indexed gathers from LDS straight into the MFMA
+//     B-operand layout: lane group r = lane/16 owns the (k2,k3) quadrant
+//     (r/2, r%2) of the NK x NK grid, lane%16 is the MFMA column (cell);
+//   * the radial contraction Q_{k1,q1} += sum R^{(c)}_{k1,(k2k3)} Phi_{(k2k3)}
+//     runs on v_mfma_f32_16x16x4_f32 (FP32) or as three split hi/lo BF16
+//     v_mfma_f32_16x16x32_bf16 products with FP32 accumulation (BF16X3);
+//   * the wave keeps the 16x16 accumulator tiles of a group of q1 values of
+//     one l1 across all channels of that l1 (the channel reduction), so every
+//     output is produced by one wave in a fixed order: results are bitwise
+//     independent of the other cells in the batch;
+//   * waves pull (l1, q1-group) work units from an LDS counter, largest first.
+// The mass, momentum and energy rows are stored as exact zeros (Section 4.4).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "wefq_core.h"
+
+namespace wefq {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline bool invariant_row(int q1, int k1) {
+  return (q1 == 0 && k1 <= 1) || (q1 >= 1 && q1 <= 3 && k1 == 0);
+}
+
+struct Fp64Params {
+  const double* f;
+  double* Q;
+  int64_t B, ldf, ldq;
+  int NK, N, nchunk;
+  const double* R;
+  const int* q1ptr;
+  const int* ent_c;
+  const uint32_t* ent_q;
+  const double* ent_g;
+};
+
+__global__ __launch_bounds__(256) void apply_fp64_kernel(Fp64Params p) {
+  const int64_t b = blockIdx.x / p.nchunk;
+  const int n = (blockIdx.x % p.nchunk) * blockDim.x + threadIdx.x;
+  if (b >= p.B || n >= p.N) return;
+  const int NK = p.NK, NK2 = NK * NK;
+  const int q1 = n / NK, k1 = n % NK;
+  const double* fb = p.f + b * p.ldf;
+  double acc = 0.0;
+  for (int e = p.q1ptr[q1]; e < p.q1ptr[q1 + 1]; ++e) {
+    const uint32_t qq = p.ent_q[e];
+    const double* f2 = fb + (int)(qq & 0xffffu) * NK;
+    const double* f3 = fb + (int)(qq >> 16) * NK;
+    const double* Rr = p.R + (int64_t)p.ent_c[e] * NK2 * NK + (int64_t)k1 * NK2;
+    double s = 0.0;
+    for (int k2 = 0; k2 < NK; ++k2) {
+      double t = 0.0;
+      for (int k3 = 0; k3 < NK; ++k3) t = fma(Rr[k2 * NK + k3], f3[k3], t);
+      s = fma(f2[k2], t, s);
+    }
+    acc = fma(p.ent_g[e], s, acc);
+  }
+  p.Q[b * p.ldq + n] = invariant_row(q1, k1) ? 0.0 : acc;
+}
+
+hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int64_t B,
+                             int64_t ldf, int64_t ldq, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  Fp64Params p;
+  p.f = f; p.Q = Q; p.B = B; p.ldf = ldf; p.ldq = ldq;
+  p.NK = h->NK; p.N = h->N; p.nchunk = (h->N + 255) / 256;
+  p.R = h->dR64; p.q1ptr = h->d_q1ptr; p.ent_c = h->d_ent_c; p.ent_q = h->d_ent_q; p.ent_g = h->d_ent_g;
+  int64_t blocks = B * p.nchunk;
+  const int64_t maxg = 0x7fffffff;
+  for (int64_t b0 = 0; b0 < B; b0 += maxg / p.nchunk) {
+    int64_t nb = B - b0 < maxg / p.nchunk ? B - b0 : maxg / p.nchunk;
+    Fp64Params q = p;
+    q.f = f + b0 * ldf; q.Q = Q + b0 * ldq; q.B = nb;
+    hipLaunchKernelGGL(apply_fp64_kernel, dim3((unsigned)(nb * p.nchunk)), dim3(256), 0, s, q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  (void)blocks;
+  return hipSuccess;
+}
+
+struct MfmaParams {
+  const float* f;
+  float* Q;
+  int64_t B, ldf, ldq;
+  int NK, NQ, N;
+  int nunits;
+  const int* units;        // [nunits][3]
+  const int* chan_begin;   // [L+2]
+  const int* slice_off;    // [NTm]
+  const int* sptr;         // slices + 1
+  const uint32_t* mq;      // q2 | q3 << 16
+  const float* mg;
+  const float* Rt32;       // [NTm][RT][H*H][64]
+  const uint16_t* Rhi;     // [NTm][RT][U][64][8]
+  const uint16_t* Rlo;
+};
+
+constexpr int GQ = 8;      // output states per work unit
+
+template <int H, int SLOTS, int RT, bool BF16>
+__global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
+  constexpr int TB = 16 / SLOTS;
+  constexpr int HH = H * H;
+  constexpr int U = (HH + 7) / 8;
+  constexpr int NP = GQ / SLOTS;
+  extern __shared__ float fs[];
+  __shared__ int unit_ctr;
+  const int NK = p.NK;
+  const int64_t cell0 = (int64_t)blockIdx.x * TB;
+  // stage the coefficient tile: fs[n * TB + cell]
+  for (int idx = threadIdx.x; idx < TB * p.N; idx += blockDim.x) {
+    const int cl = idx / p.N, n = idx - cl * p.N;
+    const int64_t cell = cell0 + cl;
+    fs[n * TB + cl] = (cell < p.B) ? p.f[cell * p.ldf + n] : 0.0f;
+  }
+  if (threadIdx.x == 0) unit_ctr = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int r = lane >> 4, j = lane & 15;
+  const int h2 = r >> 1, h3 = r & 1;
+  const int cellj = j % TB, slot = j / TB;
+  int k2off[H], k3off[H];
+#pragma unroll
+  for (int a = 0; a < H; ++a) {
+    int k2 = h2 * H + a; k2 = k2 < NK ? k2 : NK - 1;
+    int k3 = h3 * H + a; k3 = k3 < NK ? k3 : NK - 1;
+    k2off[a] = k2 * TB + cellj;
+    k3off[a] = k3 * TB + cellj;
+  }
+  const int rowstride = NK * TB;
+  while (true) {
+    int u = 0;
+    if (lane == 0) u = atomicAdd(&unit_ctr, 1);
+    u = __shfl(u, 0);
+    if (u >= p.nunits) break;
+    const int l1 = p.units[3 * u], qb = p.units[3 * u + 1], nq = p.units[3 * u + 2];
+    v4f acc[NP][RT];
+#pragma unroll
+    for (int gi = 0; gi < NP; ++gi)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[gi][rt] = (v4f){0.f, 0.f, 0.f, 0.f};
+    const int cb = p.chan_begin[l1], ce = p.chan_begin[l1 + 1];
+    for (int ct = cb; ct < ce; ++ct) {
+      const int soff = p.slice_off[ct] - l1 * l1;
+#pragma unroll
+      for (int gi = 0; gi < NP; ++gi) {
+        if (gi * SLOTS >= nq) break;
+        const int qi = gi * SLOTS + slot;
+        const bool qvalid = qi < nq;
+        const int s = soff + qb + (qvalid ? qi : 0);
+        int e0 = p.sptr[s], e1 = p.sptr[s + 1];
+        if (!qvalid) e1 = e0;
+        if (SLOTS == 1) {               // the slice is shared by the whole wave
+          e0 = __builtin_amdgcn_readfirstlane(e0);
+          e1 = __builtin_amdgcn_readfirstlane(e1);
+        }
+        float phi[U * 8];
+#pragma unroll
+        for (int t = 0; t < U * 8; ++t) phi[t] = 0.0f;
+        if (SLOTS == 1) {
+          for (int e = e0; e < e1; ++e) {
+            const uint32_t qq = p.mq[e];
+            const float gg = p.mg[e];
+            const float* f2 = fs + (int)(qq & 0xffffu) * rowstride;
+            const float* f3 = fs + (int)(qq >> 16) * rowstride;
+            float uu[H], ww[H];
+#pragma unroll
+            for (int a = 0; a < H; ++a) { uu[a] = gg * f2[k2off[a]]; ww[a] = f3[k3off[a]]; }
+#pragma unroll
+            for (int a = 0; a < H; ++a)
+#pragma unroll
+              for (int b = 0; b < H; ++b) phi[a * H + b] = fmaf(uu[a], ww[b], phi[a * H + b]);
+          }
+        } else {
+          const int len = e1 - e0;
+          const int other = __shfl_xor(len, 8);
+          const int maxlen = len > other ? len : other;
+          for (int i = 0; i < maxlen; ++i) {
+            const bool in = i < len;
+            const int e = in ? e0 + i : e0;
+            const uint32_t qq = in ? p.mq[e] : 0u;
+            const float gg = in ? p.mg[e] : 0.0f;
+            const float* f2 = fs + (int)(qq & 0xffffu) * rowstride;
+            const float* f3 = fs + (int)(qq >> 16) * rowstride;
+            float uu[H], ww[H];
+#pragma unroll
+            for (int a = 0; a < H; ++a) { uu[a] = gg * f2[k2off[a]]; ww[a] = f3[k3off[a]]; }
+#pragma unroll
+            for (int a = 0; a < H; ++a)
+#pragma unroll
+              for (int b = 0; b < H; ++b) phi[a * H + b] = fmaf(uu[a], ww[b], phi[a * H + b]);
+          }
+        }
+        if (!BF16) {
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            const float* At = p.Rt32 + ((int64_t)(ct * RT + rt) * HH) * 64 + lane;
+#pragma unroll
+            for (int t = 0; t < HH; ++t)
+              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(At[t * 64], phi[t], acc[gi][rt], 0, 0, 0);
+          }
+        } else {
+#pragma unroll
+          for (int uu8 = 0; uu8 < U; ++uu8) {
+            v8bf bh, bl;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const float x = phi[uu8 * 8 + e];
+              const __bf16 xh = (__bf16)x;
+              bh[e] = xh;
+              bl[e] = (__bf16)(x - (float)xh);
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) {
+              const int64_t off = (((int64_t)(ct * RT + rt) * U + uu8) * 64 + lane) * 8;
+              const v8bf ah = *reinterpret_cast<const v8bf*>(p.Rhi + off);
+              const v8bf al = *reinterpret_cast<const v8bf*>(p.Rlo + off);
+              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[gi][rt], 0, 0, 0);
+              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[gi][rt], 0, 0, 0);
+              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[gi][rt], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    // write the accumulator tiles: lane holds rows 4*(lane/16)+i, column lane%16
+    const int64_t cell = cell0 + cellj;
+#pragma unroll
+    for (int gi = 0; gi < NP; ++gi) {
+      const int qi = gi * SLOTS + slot;
+      if (qi >= nq || cell >= p.B) continue;
+      const int q1 = qb + qi;
+      float* dst = p.Q + cell * p.ldq + (int64_t)q1 * NK;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k1 = rt * 16 + 4 * r + i;
+          if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? 0.0f : acc[gi][rt][i];
+        }
+    }
+  }
+}
+
+template <int H, int SLOTS, int RT>
+static hipError_t launch_mfma_t(const MfmaParams& p, int precision, int64_t ntiles, int block,
+                                size_t lds, hipStream_t s) {
+  if (precision == 4) {
+    auto k = apply_mfma_kernel<H, SLOTS, RT, true>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(block), lds, s, p);
+  } else {
+    auto k = apply_mfma_kernel<H, SLOTS, RT, false>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(block), lds, s, p);
+  }
+  return hipGetLastError();
+}
+
+template <int H>
+static hipError_t launch_mfma_h(const MfmaParams& p, int precision, int slots, int rt, int64_t ntiles,
+                                int block, size_t lds, hipStream_t s) {
+  if (rt == 2) {
+    if constexpr (H >= 8) {
+      return slots == 1 ? launch_mfma_t<H, 1, 2>(p, precision, ntiles, block, lds, s)
+                        : launch_mfma_t<H, 2, 2>(p, precision, ntiles, block, lds, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  return slots == 1 ? launch_mfma_t<H, 1, 1>(p, precision, ntiles, block, lds, s)
+                    : launch_mfma_t<H, 2, 1>(p, precision, ntiles, block, lds, s);
+}
+
+hipError_t launch_apply_mfma(const wefq_core* h, int precision, const float* f, float* Q, int64_t B,
+                             int64_t ldf, int64_t ldq, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  MfmaParams p;
+  p.f = f; p.Q = Q; p.B = B; p.ldf = ldf; p.ldq = ldq;
+  p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
+  p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
+  p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mg = h->d_mg;
+  p.Rt32 = h->d_Rt32; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
+  const int TB = 16 / h->SLOTS;
+  const int64_t ntiles = (B + TB - 1) / TB;
+  const size_t lds = (size_t)h->N * TB * sizeof(float);
+  switch (h->H) {
+    case 1: return launch_mfma_h<1>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 2: return launch_mfma_h<2>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 3: return launch_mfma_h<3>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 4: return launch_mfma_h<4>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 5: return launch_mfma_h<5>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 6: return launch_mfma_h<6>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 7: return launch_mfma_h<7>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 8: return launch_mfma_h<8>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 9: return launch_mfma_h<9>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------- conservation check
+__global__ void check_kernel(const void* Q, int precision, int64_t B, int64_t ldq, int NK, int L,
+                             double* out) {
+  __shared__ double red[256];
+  double m = 0.0;
+  int rows[5] = {0, 1, NK, 2 * NK, 3 * NK};
+  int nrows = 1 + (NK > 1 ? 1 : 0);
+  if (L >= 1) { rows[nrows] = NK; rows[nrows + 1] = 2 * NK; rows[nrows + 2] = 3 * NK; nrows += 3; }
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += (int64_t)gridDim.x * blockDim.x) {
+    for (int i = 0; i < nrows; ++i) {
+      double v = precision == 1 ? ((const double*)Q)[b * ldq + rows[i]]
+                                : (double)((const float*)Q)[b * ldq + rows[i]];
+      v = fabs(v);
+      m = (v > m || v != v) ? v : m;
+    }
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      double a = red[threadIdx.x], b2 = red[threadIdx.x + st];
+      red[threadIdx.x] = (b2 > a || b2 != b2) ? b2 : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+hipError_t launch_check(const wefq_core* h, int precision, const void* Q, int64_t B, int64_t ldq,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(check_kernel, dim3(h->check_blocks), dim3(256), 0, s, Q, precision, B, ldq,
+                     h->NK, h->L, h->d_check);
+  return hipGetLastError();
+}
+
+}  // namespace wefq

@@ -1,0 +1,409 @@
+// C ABI of the wefq library: core construction, table preparation, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/wefq.h"
+#include "wefq_core.h"
+
+namespace wefq {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static uint16_t bf16_bits(float x) {       // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float bf16_to_float(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+static void zero_invariants(wefq_core* h) {
+  const int NK = h->NK;
+  const size_t blk = (size_t)NK * NK * NK;
+  for (int c = 0; c < h->NT; ++c) {
+    double* R = h->R64.data() + c * blk;
+    const Channel& ch = h->chans[c];
+    if (ch.l1 == 0 || ch.l1 == 1)                      // mass (l1=0), momentum (l1=1): k1 = 0
+      for (int i = 0; i < NK * NK; ++i) R[i] = 0.0;
+    if (ch.l1 == 0 && NK > 1)                          // energy: k1 = 1
+      for (int i = 0; i < NK * NK; ++i) R[NK * NK + i] = 0.0;
+    if (ch.l1 == 0 && ch.l2 == 0 && ch.l3 == 0)        // detailed balance: R_{k1,0,0} = 0
+      for (int k1 = 0; k1 < NK; ++k1) R[(size_t)k1 * NK * NK] = 0.0;
+  }
+}
+
+template <typename T>
+static bool upload(wefq_core* h, T*& dst, const std::vector<T>& src, hipStream_t s) {
+  dst = dev_alloc<T>(h, src.size());
+  if (!dst) { set_error("device allocation failed"); return false; }
+  if (src.empty()) return true;
+  if (hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess) {
+    set_error("host to device copy failed");
+    return false;
+  }
+  return true;
+}
+
+bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t s) {
+  const int NK = h->NK, NQ = h->NQ, L = h->L;
+  const size_t blk = (size_t)NK * NK * NK;
+  // ---- FP64 plain path: rows grouped by q1 (stable: keeps channel order)
+  std::vector<int> order(coo.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (coo[a].q1 != coo[b].q1) return coo[a].q1 < coo[b].q1;
+    return coo[a].c < coo[b].c;
+  });
+  std::vector<int> q1ptr(NQ + 1, 0), ec(coo.size());
+  std::vector<uint32_t> eq(coo.size());
+  std::vector<double> eg(coo.size());
+  for (size_t i = 0; i < order.size(); ++i) {
+    const CooRow& r = coo[order[i]];
+    q1ptr[r.q1 + 1]++;
+    ec[i] = r.c;
+    eq[i] = (uint32_t)r.q2 | ((uint32_t)r.q3 << 16);
+    eg[i] = r.g;
+  }
+  for (int q = 0; q < NQ; ++q) q1ptr[q + 1] += q1ptr[q];
+  if (!upload(h, h->dR64, h->R64, s) || !upload(h, h->d_q1ptr, q1ptr, s) || !upload(h, h->d_ent_c, ec, s) ||
+      !upload(h, h->d_ent_q, eq, s) || !upload(h, h->d_ent_g, eg, s))
+    return false;
+  // ---- merged channels (l2 <= l3), in paper order (sorted by l1)
+  std::vector<int> cidx((L + 1) * (L + 1) * (L + 1), -1);
+  for (int c = 0; c < h->NT; ++c) {
+    const Channel& ch = h->chans[c];
+    cidx[(ch.l1 * (L + 1) + ch.l2) * (L + 1) + ch.l3] = c;
+  }
+  std::vector<int> mchan;                      // paper channel of each merged channel
+  std::vector<int> merged_of(h->NT, -1);
+  for (int c = 0; c < h->NT; ++c)
+    if (h->chans[c].l2 <= h->chans[c].l3) { merged_of[c] = (int)mchan.size(); mchan.push_back(c); }
+  const int NTm = (int)mchan.size();
+  h->NTm = NTm;
+  std::vector<double> Rm((size_t)NTm * blk);
+  for (int m = 0; m < NTm; ++m) {
+    const Channel& ch = h->chans[mchan[m]];
+    const double* Ra = h->R64.data() + (size_t)mchan[m] * blk;
+    const double* Rb = ch.l2 < ch.l3 ? h->R64.data() + (size_t)cidx[(ch.l1 * (L + 1) + ch.l3) * (L + 1) + ch.l2] * blk : Ra;
+    double sc = ch.l2 < ch.l3 ? 1.0 : 0.5;
+    for (int k1 = 0; k1 < NK; ++k1)
+      for (int k2 = 0; k2 < NK; ++k2)
+        for (int k3 = 0; k3 < NK; ++k3)
+          Rm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3] =
+              ch.l2 < ch.l3 ? Ra[((size_t)k1 * NK + k2) * NK + k3] + Rb[((size_t)k1 * NK + k3) * NK + k2]
+                            : sc * (Ra[((size_t)k1 * NK + k2) * NK + k3] + Ra[((size_t)k1 * NK + k3) * NK + k2]);
+  }
+  std::vector<int> chan_begin(L + 2, 0);
+  for (int m = 0; m < NTm; ++m) chan_begin[h->chans[mchan[m]].l1 + 1]++;
+  for (int l = 0; l <= L; ++l) chan_begin[l + 1] += chan_begin[l];
+  // slices (merged channel, m1) with merged rows
+  std::vector<std::vector<std::pair<uint32_t, double>>> slices;
+  std::vector<int> slice_off(NTm);
+  for (int m = 0; m < NTm; ++m) {
+    slice_off[m] = (int)slices.size();
+    slices.resize(slices.size() + 2 * h->chans[mchan[m]].l1 + 1);
+  }
+  int ngm = 0;
+  for (const CooRow& r : coo) {
+    int m = merged_of[r.c];
+    if (m < 0) continue;                        // carried by the partner channel
+    const Channel& ch = h->chans[r.c];
+    double g = r.g;
+    if (ch.l2 == ch.l3) {
+      if (r.q2 > r.q3) continue;
+      if (r.q2 < r.q3) g *= 2.0;
+    }
+    slices[slice_off[m] + (r.q1 - ch.l1 * ch.l1)].push_back({(uint32_t)r.q2 | ((uint32_t)r.q3 << 16), g});
+    ++ngm;
+  }
+  std::vector<int> sptr(slices.size() + 1, 0);
+  std::vector<uint32_t> mq;
+  std::vector<float> mg;
+  int nsm = 0;
+  for (size_t i = 0; i < slices.size(); ++i) {
+    auto& sl = slices[i];
+    std::sort(sl.begin(), sl.end(), [](const std::pair<uint32_t, double>& a, const std::pair<uint32_t, double>& b) {
+      return (a.first >> 16) != (b.first >> 16) ? (a.first >> 16) < (b.first >> 16) : (a.first & 0xffff) < (b.first & 0xffff);
+    });
+    for (auto& e : sl) { mq.push_back(e.first); mg.push_back((float)e.second); }
+    sptr[i + 1] = (int)mq.size();
+    if (!sl.empty()) ++nsm;
+  }
+  for (int pad = 0; pad < 8; ++pad) { mq.push_back(0u); mg.push_back(0.0f); }  // tail slack for predicated loads
+  h->NGm = ngm;
+  h->NSm = nsm;
+  // MFMA geometry
+  h->H = (NK + 1) / 2;
+  h->RT = NK > 16 ? 2 : 1;
+  int dev_lds = 0;
+  if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess || dev_lds <= 0)
+    dev_lds = 65536;
+  const size_t limit = (size_t)std::min(dev_lds, 163840) - 512;
+  if ((size_t)h->N * 16 * 4 <= limit) { h->SLOTS = 1; h->TB = 16; }
+  else if ((size_t)h->N * 8 * 4 <= limit) { h->SLOTS = 2; h->TB = 8; }
+  else { h->SLOTS = 0; h->TB = 0; }
+  const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;
+  auto Rval = [&](int m, int k1, int t, int r) -> double {
+    int k2 = (r >> 1) * H + t / H, k3 = (r & 1) * H + t % H;
+    if (k1 >= NK || k2 >= NK || k3 >= NK || t >= HH) return 0.0;
+    return Rm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3];
+  };
+  bool want32 = h->precisions & WEFQ_FP32, want16 = h->precisions & WEFQ_BF16X3;
+  if ((want32 || want16) && h->SLOTS == 0) {
+    set_error("coefficient tile does not fit in LDS for this truncation");
+    return false;
+  }
+  if (want32) {
+    std::vector<float> t32((size_t)NTm * RT * HH * 64);
+    for (int m = 0; m < NTm; ++m)
+      for (int rt = 0; rt < RT; ++rt)
+        for (int t = 0; t < HH; ++t)
+          for (int ln = 0; ln < 64; ++ln)
+            t32[(((size_t)m * RT + rt) * HH + t) * 64 + ln] = (float)Rval(m, rt * 16 + (ln & 15), t, ln >> 4);
+    if (!upload(h, h->d_Rt32, t32, s)) return false;
+  }
+  if (want16) {
+    std::vector<uint16_t> hi((size_t)NTm * RT * UU * 64 * 8), lo(hi.size());
+    for (int m = 0; m < NTm; ++m)
+      for (int rt = 0; rt < RT; ++rt)
+        for (int u = 0; u < UU; ++u)
+          for (int ln = 0; ln < 64; ++ln)
+            for (int e = 0; e < 8; ++e) {
+              double v = Rval(m, rt * 16 + (ln & 15), u * 8 + e, ln >> 4);
+              uint16_t bh = bf16_bits((float)v);
+              uint16_t bl = bf16_bits((float)(v - (double)bf16_to_float(bh)));
+              size_t idx = ((((size_t)m * RT + rt) * UU + u) * 64 + ln) * 8 + e;
+              hi[idx] = bh; lo[idx] = bl;
+            }
+    if (!upload(h, h->d_Rhi, hi, s) || !upload(h, h->d_Rlo, lo, s)) return false;
+  }
+  // work units: (l1, first q1, count), largest estimated cost first
+  h->GQ = 8;
+  struct Unit { int l1, qb, nq; double cost; };
+  std::vector<Unit> units;
+  for (int l1 = 0; l1 <= L; ++l1) {
+    for (int qb = l1 * l1; qb < (l1 + 1) * (l1 + 1); qb += h->GQ) {
+      int nq = std::min(h->GQ, (l1 + 1) * (l1 + 1) - qb);
+      double cost = 0;
+      for (int m = chan_begin[l1]; m < chan_begin[l1 + 1]; ++m)
+        for (int q = qb; q < qb + nq; ++q) {
+          int si = slice_off[m] + q - l1 * l1;
+          cost += (double)(sptr[si + 1] - sptr[si]) * (HH + 2 * H) + HH * RT * 8.0;
+        }
+      units.push_back({l1, qb, nq, cost});
+    }
+  }
+  std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+  std::vector<int> uarr;
+  for (auto& u : units) { uarr.push_back(u.l1); uarr.push_back(u.qb); uarr.push_back(u.nq); }
+  h->nunits = (int)units.size();
+  if (!upload(h, h->d_units, uarr, s) || !upload(h, h->d_chan_begin, chan_begin, s) ||
+      !upload(h, h->d_slice_off, slice_off, s) || !upload(h, h->d_sptr, sptr, s) ||
+      !upload(h, h->d_mq, mq, s) || !upload(h, h->d_mg, mg, s))
+    return false;
+  h->d_check = dev_alloc<double>(h, h->check_blocks);
+  if (!h->d_check) { set_error("device allocation failed"); return false; }
+  return hipStreamSynchronize(s) == hipSuccess;
+}
+
+}  // namespace wefq
+
+using namespace wefq;
+
+static wefq_status fail(wefq_status st, const std::string& msg) {
+  set_error(msg);
+  return st;
+}
+
+static void free_core(wefq_core* h) {
+  if (!h) return;
+  for (void* p : h->allocations) (void)hipFree(p);
+  delete h;
+}
+
+extern "C" {
+
+const char* wefq_last_error(void) { return g_last_error.c_str(); }
+
+wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handle* out) {
+  try {
+    if (!desc || !out) return fail(WEFQ_EINVAL, "null descriptor or output pointer");
+    *out = nullptr;
+    if (desc->Kmax < 0 || desc->Kmax > 16 || desc->Lmax < 0 || desc->Lmax > 16)
+      return fail(WEFQ_EUNSUPPORTED, "Kmax and Lmax must lie in [0, 16]");
+    double gamma;
+    switch (desc->model) {
+      case WEFQ_MAXWELL: gamma = 0.0; break;
+      case WEFQ_HARD_SPHERE: gamma = 1.0; break;
+      case WEFQ_VHS: gamma = desc->gamma; break;
+      default: return fail(WEFQ_EINVAL, "unknown collision model");
+    }
+    if (!(gamma >= 0.0 && gamma <= 2.0)) return fail(WEFQ_EINVAL, "gamma must lie in [0, 2]");
+    unsigned prec = desc->precisions ? desc->precisions : (WEFQ_FP64 | WEFQ_FP32 | WEFQ_BF16X3);
+    if (prec & ~7u) return fail(WEFQ_EINVAL, "unknown precision bits");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(WEFQ_EHIP, "no HIP device available");
+    if (desc->device < 0 || desc->device >= ndev) return fail(WEFQ_EINVAL, "device ordinal out of range");
+    if (hipSetDevice(desc->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+    wefq_core* h = new (std::nothrow) wefq_core();
+    if (!h) return fail(WEFQ_ENOMEM, "host allocation failed");
+    h->device = desc->device;
+    h->K = desc->Kmax; h->L = desc->Lmax; h->NK = h->K + 1; h->NQ = (h->L + 1) * (h->L + 1);
+    h->N = h->NK * h->NQ;
+    h->gamma = gamma;
+    h->b0 = desc->b0 > 0 ? desc->b0 : 1.0 / (4.0 * 3.141592653589793238462643383279502884);
+    h->precisions = prec;
+    h->chans = enumerate_channels(h->L);
+    h->NT = (int)h->chans.size();
+    std::vector<CooRow> coo = build_coo(h->L);
+    h->NG = (int)coo.size();
+    {
+      std::vector<char> seen((size_t)h->NT * h->NQ, 0);
+      int ns = 0;
+      for (auto& r : coo) if (!seen[(size_t)r.c * h->NQ + r.q1]) { seen[(size_t)r.c * h->NQ + r.q1] = 1; ++ns; }
+      h->NS = ns;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!build_radial_core(h, coo, s)) { free_core(h); return WEFQ_EHIP; }
+    zero_invariants(h);
+    if (!prepare_apply_tables(h, coo, s)) { free_core(h); return WEFQ_ENOMEM; }
+    *out = h;
+    return WEFQ_OK;
+  } catch (const std::exception& e) {
+    return fail(WEFQ_EINVAL, std::string("exception in core build: ") + e.what());
+  } catch (...) {
+    return fail(WEFQ_EINVAL, "unknown exception in core build");
+  }
+}
+
+wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info) {
+  if (!h || !info) return fail(WEFQ_EINVAL, "null handle or info pointer");
+  info->N = h->N; info->NK = h->NK; info->NQ = h->NQ;
+  info->N_T = h->NT; info->N_G = h->NG; info->N_S = h->NS;
+  info->N_T_merged = h->NTm; info->N_G_merged = h->NGm; info->N_S_merged = h->NSm;
+  info->quad_nodes = h->quad_nodes;
+  info->device_bytes = h->device_bytes;
+  double nk = h->NK;
+  info->flop_alg_per_cell = 2.0 * nk * nk * h->NG + 2.0 * nk * nk * nk * h->NS;
+  info->gamma = h->gamma; info->b0 = h->b0;
+  return WEFQ_OK;
+}
+
+wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count) {
+  if (!h || !host_R) return fail(WEFQ_EINVAL, "null handle or output pointer");
+  if (count != (int64_t)h->R64.size()) return fail(WEFQ_EINVAL, "count must equal N_T * NK^3");
+  std::memcpy(host_R, h->R64.data(), h->R64.size() * sizeof(double));
+  return WEFQ_OK;
+}
+
+static wefq_status check_batch(wefq_handle h, int32_t precision, const void* a, const void* b, int64_t B,
+                               int64_t lda, int64_t ldb) {
+  if (!h) return fail(WEFQ_EINVAL, "null handle");
+  if (precision != WEFQ_FP64 && precision != WEFQ_FP32 && precision != WEFQ_BF16X3)
+    return fail(WEFQ_EINVAL, "unknown precision");
+  if (!(h->precisions & (unsigned)precision)) return fail(WEFQ_EINVAL, "precision was not prepared for this core");
+  if (B < 0) return fail(WEFQ_EINVAL, "negative batch size");
+  if (B == 0) return WEFQ_OK;
+  if (!a) return fail(WEFQ_EINVAL, "null input pointer");
+  if (lda < h->N || ldb < h->N) return fail(WEFQ_EINVAL, "leading dimension smaller than N");
+  if (((uintptr_t)a & 15) || (b && ((uintptr_t)b & 15))) return fail(WEFQ_EINVAL, "pointers must be 16-byte aligned");
+  return WEFQ_OK;
+}
+
+wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* Q, int64_t B, int64_t ld_f,
+                         int64_t ld_q, void* stream) {
+  wefq_status st = check_batch(h, precision, f, Q, B, ld_f, ld_q);
+  if (st != WEFQ_OK || B == 0) return st;
+  if (!Q) return fail(WEFQ_EINVAL, "null output pointer");
+  size_t es = precision == WEFQ_FP64 ? 8 : 4;
+  const char* fb = (const char*)f; const char* qb = (const char*)Q;
+  if (fb < qb + (size_t)B * ld_q * es && qb < fb + (size_t)B * ld_f * es)
+    return fail(WEFQ_EINVAL, "f and Q must not overlap");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+  hipError_t e;
+  if (precision == WEFQ_FP64)
+    e = launch_apply_fp64(h, (const double*)f, (double*)Q, B, ld_f, ld_q, (hipStream_t)stream);
+  else
+    e = launch_apply_mfma(h, precision, (const float*)f, (float*)Q, B, ld_f, ld_q, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return WEFQ_OK;
+}
+
+wefq_status wefq_check_conservation(wefq_handle h, int32_t precision, const void* Q, int64_t B, int64_t ld_q,
+                                    double* max_abs, void* stream) {
+  if (!max_abs) return fail(WEFQ_EINVAL, "null result pointer");
+  wefq_status st = check_batch(h, precision, Q, nullptr, B, ld_q, ld_q);
+  if (st != WEFQ_OK) return st;
+  *max_abs = 0.0;
+  if (B == 0) return WEFQ_OK;
+  if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_check(h, precision, Q, B, ld_q, s);
+  std::vector<double> part(h->check_blocks);
+  if (e == hipSuccess) e = hipMemcpyAsync(part.data(), h->d_check, part.size() * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("conservation check: ") + hipGetErrorString(e));
+  double m = 0.0;
+  for (double v : part) m = (v > m || v != v) ? v : m;
+  *max_abs = m;
+  return WEFQ_OK;
+}
+
+wefq_status wefq_destroy(wefq_handle h) {
+  if (!h) return fail(WEFQ_EINVAL, "null handle");
+  (void)hipSetDevice(h->device);
+  free_core(h);
+  return WEFQ_OK;
+}
+
+wefq_status wefq_host_coo(int32_t Lmax, int64_t* count, int32_t* q1, int32_t* q2, int32_t* q3, int32_t* channel,
+                          double* g) {
+  try {
+    if (!count) return fail(WEFQ_EINVAL, "null count pointer");
+    if (Lmax < 0 || Lmax > 16) return fail(WEFQ_EUNSUPPORTED, "Lmax must lie in [0, 16]");
+    std::vector<CooRow> rows = build_coo(Lmax);
+    if (!q1 && !q2 && !q3 && !channel && !g) { *count = (int64_t)rows.size(); return WEFQ_OK; }
+    if (*count < (int64_t)rows.size()) return fail(WEFQ_EINVAL, "output arrays too small");
+    for (size_t i = 0; i < rows.size(); ++i) {
+      if (q1) q1[i] = rows[i].q1;
+      if (q2) q2[i] = rows[i].q2;
+      if (q3) q3[i] = rows[i].q3;
+      if (channel) channel[i] = rows[i].c;
+      if (g) g[i] = rows[i].g;
+    }
+    *count = (int64_t)rows.size();
+    return WEFQ_OK;
+  } catch (...) {
+    return fail(WEFQ_EINVAL, "exception while building the COO table");
+  }
+}
+
+wefq_status wefq_host_gauss(int32_t kind, int32_t n, double alpha, double* x, double* w) {
+  try {
+    if (!x || !w) return fail(WEFQ_EINVAL, "null output pointer");
+    if ((kind != 0 && kind != 1) || n < 1 || n > 512 || (kind == 1 && alpha <= -1.0))
+      return fail(WEFQ_EINVAL, "bad quadrature request");
+    std::vector<double> xs, ws;
+    gauss_rule(kind, n, alpha, xs, ws);
+    std::memcpy(x, xs.data(), n * 8);
+    std::memcpy(w, ws.data(), n * 8);
+    return WEFQ_OK;
+  } catch (...) {
+    return fail(WEFQ_EINVAL, "quadrature failed");
+  }
+}
+
+}  // extern "C"

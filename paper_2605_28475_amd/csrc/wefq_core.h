@@ -1,0 +1,83 @@
+// Internal representation of a built core (the opaque wefq_handle).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "wefq_host.h"
+
+struct wefq_core {
+  int device = 0;
+  int K = 0, L = 0, NK = 0, NQ = 0, N = 0;
+  int NT = 0, NG = 0, NS = 0;          // paper counts
+  int NTm = 0, NGm = 0, NSm = 0;       // merged counts
+  double gamma = 0.0, b0 = 0.0;
+  unsigned precisions = 0;
+  int64_t quad_nodes = 0;
+  int64_t device_bytes = 0;
+  std::vector<wefq::Channel> chans;
+  std::vector<double> R64;             // host copy, zeroed, [c][k1][k2][k3]
+
+  // FP64 plain path: COO rows grouped by q1 (CSR), paper channel ids
+  double* dR64 = nullptr;
+  int* d_q1ptr = nullptr;              // NQ + 1
+  int* d_ent_c = nullptr;              // N_G
+  uint32_t* d_ent_q = nullptr;         // q2 | q3 << 16
+  double* d_ent_g = nullptr;
+
+  // MFMA path (merged channels sorted by l1)
+  int H = 0, RT = 0, TB = 0, SLOTS = 0;
+  int* d_chan_begin = nullptr;         // L + 2: merged channels of l1 are [begin[l1], begin[l1+1])
+  int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
+  int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
+  uint32_t* d_mq = nullptr;            // merged entries: q2 | q3 << 16
+  float* d_mg = nullptr;               // merged weights
+  float* d_Rt32 = nullptr;             // [NTm][RT][H*H][64]
+  uint16_t* d_Rhi = nullptr;           // [NTm][RT][ceil(H*H/8)][64][8] bf16 bits
+  uint16_t* d_Rlo = nullptr;
+  int* d_units = nullptr;              // [nunits][3]: l1, q1 begin, count
+  int nunits = 0;
+  int GQ = 0;                          // q1 per unit
+  int block = 512;                     // threads per workgroup of the MFMA kernel
+
+  // conservation check scratch
+  double* d_check = nullptr;
+  int check_blocks = 256;
+
+  std::vector<void*> allocations;
+};
+
+namespace wefq {
+
+// Error reporting helper (thread-local message).
+void set_error(const std::string& msg);
+
+// Allocate device memory recorded in the handle.
+template <typename T>
+T* dev_alloc(wefq_core* h, size_t count) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+  h->allocations.push_back(p);
+  h->device_bytes += (int64_t)(count * sizeof(T));
+  return (T*)p;
+}
+
+// FP64 radial core on the device: fills h->R64 (not yet zeroed) on the host.
+// Returns false (with set_error) on failure.
+bool build_radial_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t stream);
+
+// Upload routing tables / MFMA tiles for the requested precisions.
+bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t stream);
+
+// Kernel launchers (apply.hip).
+hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int64_t B,
+                             int64_t ldf, int64_t ldq, hipStream_t s);
+hipError_t launch_apply_mfma(const wefq_core* h, int precision, const float* f, float* Q,
+                             int64_t B, int64_t ldf, int64_t ldq, hipStream_t s);
+hipError_t launch_check(const wefq_core* h, int precision, const void* Q, int64_t B,
+                        int64_t ldq, hipStream_t s);
+
+}  // namespace wefq

@@ -1,0 +1,174 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, invariant_indices, rel_err, say, torch
+from oracle import apply as oapply
+from oracle import core as ocore
+from oracle_cache import coo, core_zeroed
+
+import paper_2605_28475_amd as wefq
+from paper_2605_28475_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 2e-4}
+_cores = {}
+
+
+def gpu_core(model, K, L, gamma=None):
+    key = (model, K, L, gamma)
+    if key not in _cores:
+        say(f"[build] {key}")
+        _cores[key] = wefq.Core(model, K, L, gamma=gamma, device=0)
+    return _cores[key]
+
+
+def run(core, c, prec):
+    d = dev()
+    if prec == "fp64":
+        return core.apply_Q(torch.tensor(c, device=d)).cpu().numpy()
+    out = core.apply_Q(torch.tensor(c, dtype=torch.float32, device=d), precision=prec)
+    return out.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("K,L,model,gamma", [(3, 3, "hs", 1.0), (3, 3, "mm", 0.0), (3, 3, "vhs", 0.5),
+                                             (4, 6, "mm", 0.0), (8, 8, "hs", 1.0), (8, 2, "hs", 1.0)])
+def test_core_matches_oracle(K, L, model, gamma):
+    say(f"[core] K={K} L={L} {model} gamma={gamma}")
+    R = gpu_core(model, K, L, gamma).download_R()
+    ref = core_zeroed(K, L, gamma)
+    assert rel_err(R, ref) < 1e-12
+
+
+def test_core_k12_vhs_sampled_channels():
+    K = L = 12
+    say("[core] K=L=12 vhs 0.5 sampled channels")
+    R = gpu_core("vhs", K, L, 0.5).download_R()
+    T = coo(L)
+    pick = [0, 1, 7, 50, 123, 300, 450, 615]
+    ref = ocore.zero_invariants(ocore.core_exact(K, L, 0.5, table=T, subset=pick), T["channels"])
+    assert rel_err(R[pick], ref[pick]) < 1e-12
+
+
+@pytest.mark.parametrize("K,L,model,gamma,B", [(3, 3, "hs", 1.0, 1), (3, 3, "hs", 1.0, 37),
+                                               (4, 4, "vhs", 0.5, 21), (8, 8, "hs", 1.0, 19),
+                                               (5, 3, "mm", 0.0, 17), (2, 7, "hs", 1.0, 5)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_apply_matches_oracle(K, L, model, gamma, B, prec):
+    say(f"[apply] K={K} L={L} {model} B={B} {prec}")
+    core = gpu_core(model, K, L, gamma)
+    c = synth.perturbed_maxwellian(K, L, B, seed=synth.BASE_SEED + 11 * K + L)
+    ref = oapply.apply_q(core_zeroed(K, L, gamma), coo(L), c, K)
+    q = run(core, c, prec)
+    assert rel_err(q, ref) < TOL[prec]
+    assert np.all(q[:, invariant_indices(K, L)] == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_unit_maxwellian_is_exact_fixed_point(prec):
+    K = L = 4
+    core = gpu_core("hs", K, L, 1.0)
+    q = run(core, synth.unit_maxwellian(K, L, 3), prec)
+    assert np.all(q == 0.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_cell_result_independent_of_batch(prec):
+    K, L = 6, 6
+    core = gpu_core("vhs", K, L, 0.5)
+    c = synth.perturbed_maxwellian(K, L, 45, seed=99)
+    full = run(core, c, prec)
+    for b in (0, 17, 44):
+        alone = run(core, c[b:b + 1], prec)
+        assert np.array_equal(alone[0], full[b])
+
+
+def test_padded_rows_zero_batch_and_errors():
+    K = L = 3
+    core = gpu_core("hs", K, L, 1.0)
+    d = dev()
+    N = core.N
+    c = synth.perturbed_maxwellian(K, L, 9, seed=5)
+    ref = run(core, c, "fp32")
+    fpad = torch.zeros((9, N + 12), dtype=torch.float32, device=d)
+    fpad[:, :N] = torch.tensor(c, dtype=torch.float32, device=d)
+    qpad = torch.full((9, N + 20), 7.0, dtype=torch.float32, device=d)
+    core.apply_Q(fpad[:, :N], out=qpad[:, :N])
+    q = qpad.cpu().numpy()
+    assert np.array_equal(q[:, :N], ref.astype(np.float32))
+    assert np.all(q[:, N:] == 7.0)
+    empty = torch.empty((0, N), dtype=torch.float32, device=d)
+    assert core.apply_Q(empty).shape == (0, N)
+    f = torch.zeros(4 * N + 1, dtype=torch.float32, device=d)
+    with pytest.raises(wefq.WefqError):
+        core.apply_Q(f[1:].view(4, N))
+    with pytest.raises(wefq.WefqError):
+        core.apply_Q(torch.zeros((2, N), dtype=torch.float64, device=d), precision="fp32")
+
+
+def test_conservation_check_kernel():
+    K = L = 5
+    core = gpu_core("hs", K, L, 1.0)
+    d = dev()
+    c = synth.perturbed_maxwellian(K, L, 300, seed=3)
+    for prec, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16x3", torch.float32)):
+        q = core.apply_Q(torch.tensor(c, dtype=dt, device=d), precision=prec)
+        assert core.check_conservation(q, precision=prec) == 0.0
+        q[123, 1] = -2.5
+        assert core.check_conservation(q, precision=prec) == 2.5
+
+
+def _wcu(k, l, b0=1 / (4 * math.pi)):
+    from scipy.special import eval_legendre, roots_legendre
+    t, w = roots_legendre(40)
+    c, s = np.sqrt((1 + t) / 2), np.sqrt((1 - t) / 2)
+    f = c ** (2 * k + l) * eval_legendre(l, c) + s ** (2 * k + l) * eval_legendre(l, s) - 1 - (k == 0 and l == 0)
+    return 2 * math.pi * b0 * float(w @ f)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wcu_spectrum_through_gpu_apply(prec):
+    """Linearized Maxwell-molecule operator by polarization: L e_j = [Q(e0+e_j) - Q(e0-e_j)]/2."""
+    K = L = 8
+    core = gpu_core("mm", K, L, 0.0)
+    N = core.N
+    e = np.eye(N)
+    cells = np.concatenate([e[0] + e, e[0] - e])
+    q = run(core, cells, prec)
+    Lm = 0.5 * (q[:N] - q[N:]).T            # column j = L e_j
+    k, l, _ = synth.mode_kl(K, L)
+    lam = np.array([_wcu(a, b) for a, b in zip(k, l)])
+    tol = 2e-13 if prec == "fp64" else 5e-6
+    assert np.abs(Lm - np.diag(lam)).max() < tol
+
+
+def test_bkw_identity_through_gpu_apply():
+    """Q(c(K))_{k00} = (2 pi b0/3)(1-K) dc_k/dK for the BKW family (Maxwell molecules)."""
+    from test_oracle import _bkw_coeffs
+    kmax, L = 8, 8
+    core = gpu_core("mm", kmax, L, 0.0)
+    Ks = np.linspace(0.55, 1.05, kmax + 4)
+    coefs = np.array([_bkw_coeffs(Kt, kmax) for Kt in Ks])
+    for Kt in (0.6, 0.8, 0.95):
+        f = np.zeros((1, core.N))
+        f[0, :kmax + 1] = _bkw_coeffs(Kt, kmax)
+        q = run(core, f, "fp64")[0]
+        dck = np.array([np.polyval(np.polyder(np.polyfit(Ks, coefs[:, k], kmax + 2)), Kt) for k in range(kmax + 1)])
+        rhs = (1 - Kt) * dck / 6.0
+        assert np.abs(q[:kmax + 1] - rhs).max() < 1e-10
+        assert np.abs(q[kmax + 1:]).max() < 1e-13
+
+
+def test_viscosity_from_gpu_core():
+    """Table 4 factors from the GPU-built hard-sphere core."""
+    Kmax = 8
+    R = gpu_core("hs", Kmax, 2, 1.0).download_R()
+    chans = coo(2)["channels"]
+    L2 = (R[chans.index((2, 0, 2))][:, 0, :] + R[chans.index((2, 2, 0))][:, :, 0]) / math.sqrt(4 * math.pi)
+    fmu = [L2[0, 0] * np.linalg.inv(L2[:K + 1, :K + 1])[0, 0] for K in range(Kmax + 1)]
+    for K, val in enumerate([1.000000, 1.014851, 1.015879, 1.016006, 1.016028]):
+        assert abs(fmu[K] - val) <= 5e-7
+    assert abs(fmu[1] - 205 / 202) < 1e-12
