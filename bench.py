@@ -1,0 +1,182 @@
+"""Benchmark: Q(f,f) cell evaluations per second at Kmax = Lmax = 12 on one MI355X.
+
+Workload: variable-hard-sphere core (gamma = 0.5), Kmax = Lmax = 12 (N = 2197 modes),
+B = 65536 cells of seeded perturbed Maxwellians, coefficients resident in HBM.
+One step = one pass of the hot path over the batch: wefq_apply_Q (FP32 angular
+coupling + FP32 MFMA radial contraction, invariant rows written as exact zeros)
+followed by the FP64 conservation check of the invariant rows.  Beside it the
+plain FP64 GPU apply (the comparator) and the split BF16x3 apply are timed, and
+the FP64 CPU oracle is timed on a bounded sample of the same cells.
+
+Prints one JSON line.  Only one GPU is supported (--gpus 1).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_steps(fn, steps, stream, torch):
+    """Per-step device time from HIP events recorded on the launch stream."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([a.elapsed_time(b) for a, b in evs])
+    return ms, wall
+
+
+def cpu_baseline(K, L, gamma, c, budget_s):
+    """The oracle's literal factorized sum on host cores, on as many cells as fit the budget."""
+    from threadpoolctl import threadpool_info
+    from oracle import apply as oapply, core as ocore, gaunt as ogaunt
+    T = ogaunt.coo(L)
+    R = ocore.zero_invariants(ocore.core_exact(K, L, gamma, table=T), T["channels"])
+    done, t0 = 0, time.perf_counter()
+    while done < len(c) and time.perf_counter() - t0 < budget_s:
+        oapply.apply_q(R, T, c[done], K)
+        done += 1
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    return {"value": done / dt, "unit": "cells/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} cells of the same batch (oracle factorized sum, Section 4.5 as written), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cells", type=int, default=65536)
+    ap.add_argument("--K", type=int, default=12)
+    ap.add_argument("--L", type=int, default=12)
+    ap.add_argument("--gamma", type=float, default=0.5)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--naive-cells", type=int, default=2048)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16x3 comparison legs")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the operator is applied per cell with no exchange between "
+              "GPUs, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_28475_amd as wefq
+    from paper_2605_28475_amd import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    K, L, B, gamma = args.K, args.L, args.cells, args.gamma
+    workload = f"vhs{gamma:g}_K{K}L{L}_B{B}"
+    log(f"[bench] building core {workload}")
+    t0 = time.perf_counter()
+    core = wefq.Core("vhs", K, L, gamma=gamma, device=0)
+    build_s = time.perf_counter() - t0
+    info = core.info
+    N = core.N
+    c = synth.perturbed_maxwellian(K, L, B, seed=synth.BASE_SEED + 3)
+    f64 = torch.tensor(c, device=dev)
+    f32 = f64.float()
+    q32 = torch.empty_like(f32)
+    check = {}
+
+    def step():
+        core.apply_Q(f32, out=q32)
+        check["max"] = core.check_conservation(q32, precision="fp32")
+
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    # kernel-only times (apply alone) from events on the launch stream
+    kms, _ = time_steps(lambda: core.apply_Q(f32, out=q32), args.steps, stream, torch)
+    value = B / (wall / args.steps)
+    flop_cell = info["flop_alg_per_cell"]
+    achieved = flop_cell * B / (np.mean(kms) * 1e-3) / 1e12
+    out = {
+        "metric": "Q(f,f) cell-evals/sec at Kmax=Lmax=12 vs plain FP64 GPU; p50/p99 latency",
+        "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": workload, "Kmax": K, "Lmax": L, "gamma": gamma, "cells": B, "modes": N,
+                   "precision": "fp32 coupling + fp32 MFMA contraction"},
+        "p50_ms": float(np.percentile(kms, 50)), "p99_ms": float(np.percentile(kms, 99)),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp32"], "traffic": None,
+                     "flop_per_cell": flop_cell, "kernel_ms": float(np.mean(kms))},
+        "conservation_max_abs": check["max"],
+        "core_build_s": build_s, "quad_nodes": info["quad_nodes"],
+    }
+    if not args.no_compare:
+        q64 = torch.empty_like(f64)
+        log("[bench] fp64 comparator (same tiled kernel in FP64 with FP64 MFMA)")
+        core.apply_Q(f64, out=q64, precision="fp64")
+        ms64, _ = time_steps(lambda: core.apply_Q(f64, out=q64, precision="fp64"), args.fp64_steps, stream, torch)
+        nb = min(args.naive_cells, B)
+        log(f"[bench] fp64 naive ordering on {nb} cells")
+        qn = torch.empty_like(f64[:nb])
+        msn, _ = time_steps(lambda: core.apply_Q(f64[:nb], out=qn, precision="fp64_naive"), 1, stream, torch)
+        naive_err = float((qn - q64[:nb]).abs().max().item() / q64[:nb].abs().max().item())
+        q16 = torch.empty_like(f32)
+        core.apply_Q(f32, out=q16, precision="bf16x3")
+        ms16, _ = time_steps(lambda: core.apply_Q(f32, out=q16, precision="bf16x3"), args.steps, stream, torch)
+        core.apply_Q(f32, out=q32)
+        torch.cuda.synchronize()
+        ref = q64.cpu().numpy()
+        scale = np.abs(ref).max()
+        err32 = np.abs(q32.cpu().numpy() - ref).max(axis=0) / scale
+        err16 = np.abs(q16.cpu().numpy() - ref).max(axis=0) / scale
+        out["fp64_plain"] = {"cells_per_s": B / (np.mean(ms64) * 1e-3), "kernel_ms": float(np.mean(ms64)),
+                             "roofline_frac": flop_cell * B / (np.mean(ms64) * 1e-3) / 1e12 / PEAK["fp64"],
+                             "kernel": "angular-first tiles, FP64 coupling + FP64 MFMA"}
+        out["fp64_naive"] = {"cells_per_s": nb / (np.mean(msn) * 1e-3), "cells": nb,
+                             "kernel": "naive ordering of the factorized sum, FP64, one thread per output",
+                             "max_rel_diff_vs_fp64": naive_err}
+        out["speedup_fp32_vs_fp64_naive"] = float((B / np.mean(kms)) / (nb / np.mean(msn)))
+        out["bf16x3"] = {"cells_per_s": B / (np.mean(ms16) * 1e-3), "kernel_ms": float(np.mean(ms16)),
+                         "p50_ms": float(np.percentile(ms16, 50)), "p99_ms": float(np.percentile(ms16, 99))}
+        out["speedup_fp32_vs_fp64_plain"] = float(np.mean(ms64) / np.mean(kms))
+        out["error_vs_fp64"] = {"fp32_max_mode": float(err32.max()), "fp32_median_mode": float(np.median(err32)),
+                                "bf16x3_max_mode": float(err16.max()), "bf16x3_median_mode": float(np.median(err16)),
+                                "normwise_fp32": float(np.linalg.norm(q32.cpu().numpy() - ref) / np.linalg.norm(ref)),
+                                "normwise_bf16x3": float(np.linalg.norm(q16.cpu().numpy() - ref) / np.linalg.norm(ref))}
+        del q64
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(K, L, gamma, c, args.cpu_budget)
+    out["host_cpu"] = {"cpu_count": os.cpu_count()}
+    core.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -49,10 +49,13 @@ typedef enum {
 } wefq_model;
 
 typedef enum {
-  WEFQ_FP64 = 1,          /* plain FP64 contraction; f and Q are double */
+  WEFQ_FP64 = 1,          /* FP64 angular coupling + FP64 MFMA radial contraction; double */
   WEFQ_FP32 = 2,          /* FP32 angular coupling + FP32 MFMA radial contraction; float */
-  WEFQ_BF16X3 = 4         /* FP32 angular coupling + split hi/lo BF16 MFMA (3 products,
+  WEFQ_BF16X3 = 4,        /* FP32 angular coupling + split hi/lo BF16 MFMA (3 products,
                              FP32 accumulation); f and Q are float */
+  WEFQ_FP64_NAIVE = 8     /* the paper's naive ordering of the factorized sum (Section 4.5.2):
+                             every COO row contracts its full K^3 block, FP64, one thread per
+                             output; a reference ordering, memory-bound on R; double */
 } wefq_precision;
 
 /* Descriptor of a radial core.  The collision kernel is B(u, cos chi) = b0 u^gamma
@@ -96,7 +99,8 @@ wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count);
 
 /* Q = Q(f, f) for B independent cells (eq. full_discrete_sum, Section 4.5).
  * f and Q are device pointers, row-major [B][ld_f] / [B][ld_q], ld >= N,
- * double for WEFQ_FP64 and float otherwise, 16-byte aligned, not aliasing.
+ * double for WEFQ_FP64 / WEFQ_FP64_NAIVE and float otherwise, 16-byte aligned,
+ * not aliasing.  Requesting WEFQ_FP64_NAIVE needs the WEFQ_FP64 tables.
  * Q is overwritten (not accumulated).  B == 0 is a no-op.  Asynchronous on
  * stream; allocates nothing.  The mass, momentum and energy rows of Q are
  * exactly 0 for every precision.  NaN/Inf in f propagate elsewhere. */

@@ -10,10 +10,10 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import BF16X3, FP32, FP64, HARD_SPHERE, MAXWELL, VHS, WefqError
+from ._lib import BF16X3, FP32, FP64, FP64_NAIVE, HARD_SPHERE, MAXWELL, VHS, WefqError
 
 MODELS = {"maxwell": MAXWELL, "mm": MAXWELL, "hard_sphere": HARD_SPHERE, "hs": HARD_SPHERE, "vhs": VHS}
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp64_naive": FP64_NAIVE}
 
 
 def num_modes(K, L):
@@ -72,7 +72,7 @@ class Core:
         squeeze = f.dim() == 1
         f2 = f.unsqueeze(0) if squeeze else f
         prec = self._prec(f2, precision)
-        want = torch.float64 if prec == FP64 else torch.float32
+        want = torch.float64 if prec in (FP64, FP64_NAIVE) else torch.float32
         if f2.dtype != want or f2.device.type != "cuda" or f2.stride(-1) != 1:
             raise ValueError(f"f must be a CUDA {want} tensor with unit stride in the last dimension")
         B = f2.shape[0]

@@ -6,7 +6,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwefq.so"
 
 WEFQ_OK, WEFQ_EINVAL, WEFQ_ENOMEM, WEFQ_EHIP, WEFQ_EUNSUPPORTED, WEFQ_EBUDGET = range(6)
 MAXWELL, HARD_SPHERE, VHS = 0, 1, 2
-FP64, FP32, BF16X3 = 1, 2, 4
+FP64, FP32, BF16X3, FP64_NAIVE = 1, 2, 4, 8
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED", 5: "EBUDGET"}
 

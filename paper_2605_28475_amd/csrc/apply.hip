@@ -2,7 +2,8 @@
 //
 // apply_fp64_kernel   the plain FP64 comparator: the paper's naive contraction
 //                     (eq. full_discrete_sum as written), one thread per output
-//                     (cell, q1, k1), looping over the COO rows of q1 and k2, k3.
+//                     (cell, q1, k1), looping over the COO rows of q1 and k2, k3;
+//                     no channel merging, no tiling, no matrix cores.
 // apply_mfma_kernel   angular-first contraction (Section 4.5.4) re-laid for CDNA4:
 //   * a workgroup owns a tile of 16 cells (8 when f does not fit in LDS; then
 //     the 16 MFMA columns are 8 cells x 2 output states) and stages their
@@ -27,6 +28,7 @@
 
 #include <cstdint>
 
+#include "../../include/wefq.h"
 #include "wefq_core.h"
 
 namespace wefq {
@@ -50,15 +52,23 @@ struct Fp64Params {
   const double* ent_g;
 };
 
+// A wavefront holds 64 cells computing the same output (q1, k1): the COO rows
+// and the rows of R they address are wave-uniform (scalar loads shared by the
+// 64 cells); each lane reads its own cell's coefficients.
 __global__ __launch_bounds__(256) void apply_fp64_kernel(Fp64Params p) {
-  const int64_t b = blockIdx.x / p.nchunk;
-  const int n = (blockIdx.x % p.nchunk) * blockDim.x + threadIdx.x;
-  if (b >= p.B || n >= p.N) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t ncb = (p.B + 63) / 64;
+  const int64_t cb = blockIdx.x % ncb;
+  const int n = (int)(blockIdx.x / ncb) * 4 + w;
+  if (n >= p.N) return;
+  const int64_t b = cb * 64 + lane;
+  const bool active = b < p.B;
   const int NK = p.NK, NK2 = NK * NK;
-  const int q1 = n / NK, k1 = n % NK;
-  const double* fb = p.f + b * p.ldf;
+  const int q1 = n / NK, k1 = n - (n / NK) * NK;
+  const double* fb = p.f + (active ? b : 0) * p.ldf;
   double acc = 0.0;
-  for (int e = p.q1ptr[q1]; e < p.q1ptr[q1 + 1]; ++e) {
+  const int e1 = p.q1ptr[q1 + 1];
+  for (int e = p.q1ptr[q1]; e < e1; ++e) {
     const uint32_t qq = p.ent_q[e];
     const double* f2 = fb + (int)(qq & 0xffffu) * NK;
     const double* f3 = fb + (int)(qq >> 16) * NK;
@@ -71,33 +81,32 @@ __global__ __launch_bounds__(256) void apply_fp64_kernel(Fp64Params p) {
     }
     acc = fma(p.ent_g[e], s, acc);
   }
-  p.Q[b * p.ldq + n] = invariant_row(q1, k1) ? 0.0 : acc;
+  if (active) p.Q[b * p.ldq + n] = invariant_row(q1, k1) ? 0.0 : acc;
 }
 
 hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int64_t B,
                              int64_t ldf, int64_t ldq, hipStream_t s) {
   if (B == 0) return hipSuccess;
   Fp64Params p;
-  p.f = f; p.Q = Q; p.B = B; p.ldf = ldf; p.ldq = ldq;
-  p.NK = h->NK; p.N = h->N; p.nchunk = (h->N + 255) / 256;
+  p.f = f; p.Q = Q; p.ldf = ldf; p.ldq = ldq;
+  p.NK = h->NK; p.N = h->N; p.nchunk = (h->N + 3) / 4;
   p.R = h->dR64; p.q1ptr = h->d_q1ptr; p.ent_c = h->d_ent_c; p.ent_q = h->d_ent_q; p.ent_g = h->d_ent_g;
-  int64_t blocks = B * p.nchunk;
-  const int64_t maxg = 0x7fffffff;
-  for (int64_t b0 = 0; b0 < B; b0 += maxg / p.nchunk) {
-    int64_t nb = B - b0 < maxg / p.nchunk ? B - b0 : maxg / p.nchunk;
+  const int64_t maxcells = (int64_t)64 * (0x7fffffff / p.nchunk);
+  for (int64_t b0 = 0; b0 < B; b0 += maxcells) {
+    const int64_t nb = B - b0 < maxcells ? B - b0 : maxcells;
     Fp64Params q = p;
     q.f = f + b0 * ldf; q.Q = Q + b0 * ldq; q.B = nb;
-    hipLaunchKernelGGL(apply_fp64_kernel, dim3((unsigned)(nb * p.nchunk)), dim3(256), 0, s, q);
+    const int64_t blocks = ((nb + 63) / 64) * p.nchunk;
+    hipLaunchKernelGGL(apply_fp64_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  (void)blocks;
   return hipSuccess;
 }
 
 struct MfmaParams {
-  const float* f;
-  float* Q;
+  const void* f;
+  void* Q;
   int64_t B, ldf, ldq;
   int NK, NQ, N;
   int nunits;
@@ -106,29 +115,45 @@ struct MfmaParams {
   const int* slice_off;    // [NTm]
   const int* sptr;         // slices + 1
   const uint32_t* mq;      // q2 | q3 << 16
-  const float* mg;
+  const float* mg;         // merged weights (FP32 / BF16X3)
+  const double* mg64;      // merged weights (FP64)
   const float* Rt32;       // [NTm][RT][H*H][64]
+  const double* Rt64;      // [NTm][RT][H*H][64]
   const uint16_t* Rhi;     // [NTm][RT][U][64][8]
   const uint16_t* Rlo;
 };
 
-constexpr int GQ = 8;      // output states per work unit
+// output states per work unit (fewer when NK > 16 needs two accumulator row tiles)
+__host__ __device__ constexpr int gq_for(int H) { return H >= 8 ? 4 : 8; }
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int H, int SLOTS, int RT, bool BF16>
+// MODE 0: FP32 MFMA, 1: split BF16x3 MFMA, 2: FP64 MFMA.
+template <int MODE> struct ModeTraits;
+template <> struct ModeTraits<0> { typedef float T; typedef v4f acc_t; };
+template <> struct ModeTraits<1> { typedef float T; typedef v4f acc_t; };
+template <> struct ModeTraits<2> { typedef double T; typedef v4d acc_t; };
+
+template <int H, int SLOTS, int RT, int MODE>
 __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
+  typedef typename ModeTraits<MODE>::T T;
+  typedef typename ModeTraits<MODE>::acc_t acc_t;
   constexpr int TB = 16 / SLOTS;
   constexpr int HH = H * H;
   constexpr int U = (HH + 7) / 8;
-  constexpr int NP = GQ / SLOTS;
-  extern __shared__ float fs[];
+  constexpr int GQ = gq_for(H);
+  constexpr int NP = GQ / SLOTS > 0 ? GQ / SLOTS : 1;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* fs = reinterpret_cast<T*>(lds_raw);
   __shared__ int unit_ctr;
+  const T* f = static_cast<const T*>(p.f);
+  T* Qo = static_cast<T*>(p.Q);
   const int NK = p.NK;
   const int64_t cell0 = (int64_t)blockIdx.x * TB;
   // stage the coefficient tile: fs[n * TB + cell]
   for (int idx = threadIdx.x; idx < TB * p.N; idx += blockDim.x) {
     const int cl = idx / p.N, n = idx - cl * p.N;
     const int64_t cell = cell0 + cl;
-    fs[n * TB + cl] = (cell < p.B) ? p.f[cell * p.ldf + n] : 0.0f;
+    fs[n * TB + cl] = (cell < p.B) ? f[cell * p.ldf + n] : T(0);
   }
   if (threadIdx.x == 0) unit_ctr = 0;
   __syncthreads();
@@ -151,11 +176,11 @@ __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
     u = __shfl(u, 0);
     if (u >= p.nunits) break;
     const int l1 = p.units[3 * u], qb = p.units[3 * u + 1], nq = p.units[3 * u + 2];
-    v4f acc[NP][RT];
+    acc_t acc[NP][RT];
 #pragma unroll
     for (int gi = 0; gi < NP; ++gi)
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[gi][rt] = (v4f){0.f, 0.f, 0.f, 0.f};
+      for (int rt = 0; rt < RT; ++rt) acc[gi][rt] = (acc_t){0, 0, 0, 0};
     const int cb = p.chan_begin[l1], ce = p.chan_begin[l1 + 1];
     for (int ct = cb; ct < ce; ++ct) {
       const int soff = p.slice_off[ct] - l1 * l1;
@@ -167,54 +192,80 @@ __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
         const int s = soff + qb + (qvalid ? qi : 0);
         int e0 = p.sptr[s], e1 = p.sptr[s + 1];
         if (!qvalid) e1 = e0;
+        T phi[U * 8];
+#pragma unroll
+        for (int t = 0; t < U * 8; ++t) phi[t] = T(0);
         if (SLOTS == 1) {               // the slice is shared by the whole wave
           e0 = __builtin_amdgcn_readfirstlane(e0);
           e1 = __builtin_amdgcn_readfirstlane(e1);
-        }
-        float phi[U * 8];
-#pragma unroll
-        for (int t = 0; t < U * 8; ++t) phi[t] = 0.0f;
-        if (SLOTS == 1) {
           for (int e = e0; e < e1; ++e) {
             const uint32_t qq = p.mq[e];
-            const float gg = p.mg[e];
-            const float* f2 = fs + (int)(qq & 0xffffu) * rowstride;
-            const float* f3 = fs + (int)(qq >> 16) * rowstride;
-            float uu[H], ww[H];
+            const T gg = MODE == 2 ? (T)p.mg64[e] : (T)p.mg[e];
+            const T* f2 = fs + (int)(qq & 0xffffu) * rowstride;
+            const T* f3 = fs + (int)(qq >> 16) * rowstride;
+            T uu[H], ww[H];
 #pragma unroll
             for (int a = 0; a < H; ++a) { uu[a] = gg * f2[k2off[a]]; ww[a] = f3[k3off[a]]; }
 #pragma unroll
             for (int a = 0; a < H; ++a)
 #pragma unroll
-              for (int b = 0; b < H; ++b) phi[a * H + b] = fmaf(uu[a], ww[b], phi[a * H + b]);
+              for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
           }
         } else {
           const int len = e1 - e0;
-          const int other = __shfl_xor(len, 8);
-          const int maxlen = len > other ? len : other;
+          int maxlen = len;
+#pragma unroll
+          for (int off = TB; off < 16; off <<= 1) {
+            const int o = __shfl_xor(maxlen, off);
+            maxlen = maxlen > o ? maxlen : o;
+          }
           for (int i = 0; i < maxlen; ++i) {
             const bool in = i < len;
             const int e = in ? e0 + i : e0;
             const uint32_t qq = in ? p.mq[e] : 0u;
-            const float gg = in ? p.mg[e] : 0.0f;
-            const float* f2 = fs + (int)(qq & 0xffffu) * rowstride;
-            const float* f3 = fs + (int)(qq >> 16) * rowstride;
-            float uu[H], ww[H];
+            const T gg = in ? (MODE == 2 ? (T)p.mg64[e] : (T)p.mg[e]) : T(0);
+            const T* f2 = fs + (int)(qq & 0xffffu) * rowstride;
+            const T* f3 = fs + (int)(qq >> 16) * rowstride;
+            T uu[H], ww[H];
 #pragma unroll
             for (int a = 0; a < H; ++a) { uu[a] = gg * f2[k2off[a]]; ww[a] = f3[k3off[a]]; }
 #pragma unroll
             for (int a = 0; a < H; ++a)
 #pragma unroll
-              for (int b = 0; b < H; ++b) phi[a * H + b] = fmaf(uu[a], ww[b], phi[a * H + b]);
+              for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
           }
         }
-        if (!BF16) {
+        if constexpr (MODE == 0) {
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) {
             const float* At = p.Rt32 + ((int64_t)(ct * RT + rt) * HH) * 64 + lane;
 #pragma unroll
-            for (int t = 0; t < HH; ++t)
-              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(At[t * 64], phi[t], acc[gi][rt], 0, 0, 0);
+            for (int t0 = 0; t0 < HH; t0 += 8) {
+              float av[8];
+#pragma unroll
+              for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0f;
+              __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int t = 0; t < 8; ++t)
+                if (t0 + t < HH)
+                  acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], phi[t0 + t], acc[gi][rt], 0, 0, 0);
+            }
+          }
+        } else if constexpr (MODE == 2) {
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            const double* At = p.Rt64 + ((int64_t)(ct * RT + rt) * HH) * 64 + lane;
+#pragma unroll
+            for (int t0 = 0; t0 < HH; t0 += 8) {
+              double av[8];
+#pragma unroll
+              for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0;
+              __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int t = 0; t < 8; ++t)
+                if (t0 + t < HH)
+                  acc[gi][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], phi[t0 + t], acc[gi][rt], 0, 0, 0);
+            }
           }
         } else {
 #pragma unroll
@@ -240,78 +291,92 @@ __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
         }
       }
     }
-    // write the accumulator tiles: lane holds rows 4*(lane/16)+i, column lane%16
+    // write the accumulator tiles: column lane%16; output register i holds row
+    // 4*(lane/16)+i for the FP32 and BF16 forms and row lane/16+4*i for the FP64 form
     const int64_t cell = cell0 + cellj;
 #pragma unroll
     for (int gi = 0; gi < NP; ++gi) {
       const int qi = gi * SLOTS + slot;
       if (qi >= nq || cell >= p.B) continue;
       const int q1 = qb + qi;
-      float* dst = p.Q + cell * p.ldq + (int64_t)q1 * NK;
+      T* dst = Qo + cell * p.ldq + (int64_t)q1 * NK;
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int k1 = rt * 16 + 4 * r + i;
-          if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? 0.0f : acc[gi][rt][i];
+          const int k1 = rt * 16 + (MODE == 2 ? r + 4 * i : 4 * r + i);
+          if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? T(0) : (T)acc[gi][rt][i];
         }
     }
   }
 }
 
-template <int H, int SLOTS, int RT>
-static hipError_t launch_mfma_t(const MfmaParams& p, int precision, int64_t ntiles, int block,
-                                size_t lds, hipStream_t s) {
-  if (precision == 4) {
-    auto k = apply_mfma_kernel<H, SLOTS, RT, true>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(block), lds, s, p);
-  } else {
-    auto k = apply_mfma_kernel<H, SLOTS, RT, false>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(block), lds, s, p);
-  }
+template <int H, int SLOTS, int RT, int MODE>
+static hipError_t launch_mfma_t(const MfmaParams& p, int64_t ntiles, int block, size_t lds, hipStream_t s) {
+  auto k = apply_mfma_kernel<H, SLOTS, RT, MODE>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(block), lds, s, p);
   return hipGetLastError();
 }
 
+template <int H, int RT, int MODE>
+static hipError_t launch_mfma_s(const MfmaParams& p, int slots, int64_t ntiles, int block, size_t lds,
+                                hipStream_t s) {
+  switch (slots) {
+    case 1: return launch_mfma_t<H, 1, RT, MODE>(p, ntiles, block, lds, s);
+    case 2: return launch_mfma_t<H, 2, RT, MODE>(p, ntiles, block, lds, s);
+    case 4: return launch_mfma_t<H, 4, RT, MODE>(p, ntiles, block, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int H>
-static hipError_t launch_mfma_h(const MfmaParams& p, int precision, int slots, int rt, int64_t ntiles,
-                                int block, size_t lds, hipStream_t s) {
+static hipError_t launch_mfma_h(const MfmaParams& p, int mode, int slots, int rt, int64_t ntiles, int block,
+                                size_t lds, hipStream_t s) {
   if (rt == 2) {
     if constexpr (H >= 8) {
-      return slots == 1 ? launch_mfma_t<H, 1, 2>(p, precision, ntiles, block, lds, s)
-                        : launch_mfma_t<H, 2, 2>(p, precision, ntiles, block, lds, s);
+      switch (mode) {
+        case 0: return launch_mfma_s<H, 2, 0>(p, slots, ntiles, block, lds, s);
+        case 1: return launch_mfma_s<H, 2, 1>(p, slots, ntiles, block, lds, s);
+        case 2: return launch_mfma_s<H, 2, 2>(p, slots, ntiles, block, lds, s);
+      }
     }
     return hipErrorInvalidValue;
   }
-  return slots == 1 ? launch_mfma_t<H, 1, 1>(p, precision, ntiles, block, lds, s)
-                    : launch_mfma_t<H, 2, 1>(p, precision, ntiles, block, lds, s);
+  switch (mode) {
+    case 0: return launch_mfma_s<H, 1, 0>(p, slots, ntiles, block, lds, s);
+    case 1: return launch_mfma_s<H, 1, 1>(p, slots, ntiles, block, lds, s);
+    case 2: return launch_mfma_s<H, 1, 2>(p, slots, ntiles, block, lds, s);
+  }
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_apply_mfma(const wefq_core* h, int precision, const float* f, float* Q, int64_t B,
+hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, void* Q, int64_t B,
                              int64_t ldf, int64_t ldq, hipStream_t s) {
   if (B == 0) return hipSuccess;
   MfmaParams p;
   p.f = f; p.Q = Q; p.B = B; p.ldf = ldf; p.ldq = ldq;
   p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
   p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
-  p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mg = h->d_mg;
-  p.Rt32 = h->d_Rt32; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
-  const int TB = 16 / h->SLOTS;
+  p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mg = h->d_mg; p.mg64 = h->d_mg64;
+  p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
+  const int mode = precision == WEFQ_FP64 ? 2 : (precision == WEFQ_BF16X3 ? 1 : 0);
+  const int slots = mode == 2 ? h->SLOTS64 : h->SLOTS;
+  if (slots == 0) return hipErrorInvalidValue;
+  const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
-  const size_t lds = (size_t)h->N * TB * sizeof(float);
+  const size_t lds = (size_t)h->N * TB * (mode == 2 ? 8 : 4);
   switch (h->H) {
-    case 1: return launch_mfma_h<1>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 2: return launch_mfma_h<2>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 3: return launch_mfma_h<3>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 4: return launch_mfma_h<4>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 5: return launch_mfma_h<5>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 6: return launch_mfma_h<6>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 7: return launch_mfma_h<7>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 8: return launch_mfma_h<8>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
-    case 9: return launch_mfma_h<9>(p, precision, h->SLOTS, h->RT, ntiles, h->block, lds, s);
+    case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 2: return launch_mfma_h<2>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 3: return launch_mfma_h<3>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 4: return launch_mfma_h<4>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 5: return launch_mfma_h<5>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 6: return launch_mfma_h<6>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 7: return launch_mfma_h<7>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 8: return launch_mfma_h<8>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 9: return launch_mfma_h<9>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -326,7 +391,7 @@ __global__ void check_kernel(const void* Q, int precision, int64_t B, int64_t ld
   if (L >= 1) { rows[nrows] = NK; rows[nrows + 1] = 2 * NK; rows[nrows + 2] = 3 * NK; nrows += 3; }
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += (int64_t)gridDim.x * blockDim.x) {
     for (int i = 0; i < nrows; ++i) {
-      double v = precision == 1 ? ((const double*)Q)[b * ldq + rows[i]]
+      double v = (precision == 1 || precision == 8) ? ((const double*)Q)[b * ldq + rows[i]]
                                 : (double)((const float*)Q)[b * ldq + rows[i]];
       v = fabs(v);
       m = (v > m || v != v) ? v : m;

@@ -132,17 +132,18 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   std::vector<int> sptr(slices.size() + 1, 0);
   std::vector<uint32_t> mq;
   std::vector<float> mg;
+  std::vector<double> mg64;
   int nsm = 0;
   for (size_t i = 0; i < slices.size(); ++i) {
     auto& sl = slices[i];
     std::sort(sl.begin(), sl.end(), [](const std::pair<uint32_t, double>& a, const std::pair<uint32_t, double>& b) {
       return (a.first >> 16) != (b.first >> 16) ? (a.first >> 16) < (b.first >> 16) : (a.first & 0xffff) < (b.first & 0xffff);
     });
-    for (auto& e : sl) { mq.push_back(e.first); mg.push_back((float)e.second); }
+    for (auto& e : sl) { mq.push_back(e.first); mg.push_back((float)e.second); mg64.push_back(e.second); }
     sptr[i + 1] = (int)mq.size();
     if (!sl.empty()) ++nsm;
   }
-  for (int pad = 0; pad < 8; ++pad) { mq.push_back(0u); mg.push_back(0.0f); }  // tail slack for predicated loads
+  for (int pad = 0; pad < 8; ++pad) { mq.push_back(0u); mg.push_back(0.0f); mg64.push_back(0.0); }  // tail slack
   h->NGm = ngm;
   h->NSm = nsm;
   // MFMA geometry
@@ -152,19 +153,34 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess || dev_lds <= 0)
     dev_lds = 65536;
   const size_t limit = (size_t)std::min(dev_lds, 163840) - 512;
-  if ((size_t)h->N * 16 * 4 <= limit) { h->SLOTS = 1; h->TB = 16; }
-  else if ((size_t)h->N * 8 * 4 <= limit) { h->SLOTS = 2; h->TB = 8; }
-  else { h->SLOTS = 0; h->TB = 0; }
+  // output states sharing the 16 MFMA columns, so that a tile of 16/SLOTS cells fits in LDS
+  auto pick_slots = [&](size_t elem) {
+    for (int sl : {1, 2, 4})
+      if ((size_t)h->N * (16 / sl) * elem <= limit) return sl;
+    return 0;
+  };
+  h->SLOTS = pick_slots(4);
+  h->SLOTS64 = pick_slots(8);
+  h->TB = h->SLOTS ? 16 / h->SLOTS : 0;
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;
   auto Rval = [&](int m, int k1, int t, int r) -> double {
     int k2 = (r >> 1) * H + t / H, k3 = (r & 1) * H + t % H;
     if (k1 >= NK || k2 >= NK || k3 >= NK || t >= HH) return 0.0;
     return Rm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3];
   };
-  bool want32 = h->precisions & WEFQ_FP32, want16 = h->precisions & WEFQ_BF16X3;
-  if ((want32 || want16) && h->SLOTS == 0) {
+  bool want32 = h->precisions & WEFQ_FP32, want16 = h->precisions & WEFQ_BF16X3, want64 = h->precisions & WEFQ_FP64;
+  if (((want32 || want16) && h->SLOTS == 0) || (want64 && h->SLOTS64 == 0)) {
     set_error("coefficient tile does not fit in LDS for this truncation");
     return false;
+  }
+  if (want64) {
+    std::vector<double> t64((size_t)NTm * RT * HH * 64);
+    for (int m = 0; m < NTm; ++m)
+      for (int rt = 0; rt < RT; ++rt)
+        for (int t = 0; t < HH; ++t)
+          for (int ln = 0; ln < 64; ++ln)
+            t64[(((size_t)m * RT + rt) * HH + t) * 64 + ln] = Rval(m, rt * 16 + (ln & 15), t, ln >> 4);
+    if (!upload(h, h->d_Rt64, t64, s) || !upload(h, h->d_mg64, mg64, s)) return false;
   }
   if (want32) {
     std::vector<float> t32((size_t)NTm * RT * HH * 64);
@@ -191,7 +207,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     if (!upload(h, h->d_Rhi, hi, s) || !upload(h, h->d_Rlo, lo, s)) return false;
   }
   // work units: (l1, first q1, count), largest estimated cost first
-  h->GQ = 8;
+  h->GQ = H >= 8 ? 4 : 8;     // must match the kernel's units (gq_for)
   struct Unit { int l1, qb, nq; double cost; };
   std::vector<Unit> units;
   for (int l1 = 0; l1 <= L; ++l1) {
@@ -253,7 +269,8 @@ wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handl
     }
     if (!(gamma >= 0.0 && gamma <= 2.0)) return fail(WEFQ_EINVAL, "gamma must lie in [0, 2]");
     unsigned prec = desc->precisions ? desc->precisions : (WEFQ_FP64 | WEFQ_FP32 | WEFQ_BF16X3);
-    if (prec & ~7u) return fail(WEFQ_EINVAL, "unknown precision bits");
+    if (prec & ~15u) return fail(WEFQ_EINVAL, "unknown precision bits");
+    if (prec & WEFQ_FP64_NAIVE) prec |= WEFQ_FP64;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(WEFQ_EHIP, "no HIP device available");
     if (desc->device < 0 || desc->device >= ndev) return fail(WEFQ_EINVAL, "device ordinal out of range");
@@ -312,9 +329,10 @@ wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count) {
 static wefq_status check_batch(wefq_handle h, int32_t precision, const void* a, const void* b, int64_t B,
                                int64_t lda, int64_t ldb) {
   if (!h) return fail(WEFQ_EINVAL, "null handle");
-  if (precision != WEFQ_FP64 && precision != WEFQ_FP32 && precision != WEFQ_BF16X3)
+  if (precision != WEFQ_FP64 && precision != WEFQ_FP32 && precision != WEFQ_BF16X3 && precision != WEFQ_FP64_NAIVE)
     return fail(WEFQ_EINVAL, "unknown precision");
-  if (!(h->precisions & (unsigned)precision)) return fail(WEFQ_EINVAL, "precision was not prepared for this core");
+  unsigned need = precision == WEFQ_FP64_NAIVE ? (unsigned)WEFQ_FP64 : (unsigned)precision;
+  if (!(h->precisions & need)) return fail(WEFQ_EINVAL, "precision was not prepared for this core");
   if (B < 0) return fail(WEFQ_EINVAL, "negative batch size");
   if (B == 0) return WEFQ_OK;
   if (!a) return fail(WEFQ_EINVAL, "null input pointer");
@@ -328,16 +346,16 @@ wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* 
   wefq_status st = check_batch(h, precision, f, Q, B, ld_f, ld_q);
   if (st != WEFQ_OK || B == 0) return st;
   if (!Q) return fail(WEFQ_EINVAL, "null output pointer");
-  size_t es = precision == WEFQ_FP64 ? 8 : 4;
+  size_t es = (precision == WEFQ_FP64 || precision == WEFQ_FP64_NAIVE) ? 8 : 4;
   const char* fb = (const char*)f; const char* qb = (const char*)Q;
   if (fb < qb + (size_t)B * ld_q * es && qb < fb + (size_t)B * ld_f * es)
     return fail(WEFQ_EINVAL, "f and Q must not overlap");
   if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
   hipError_t e;
-  if (precision == WEFQ_FP64)
+  if (precision == WEFQ_FP64_NAIVE)
     e = launch_apply_fp64(h, (const double*)f, (double*)Q, B, ld_f, ld_q, (hipStream_t)stream);
   else
-    e = launch_apply_mfma(h, precision, (const float*)f, (float*)Q, B, ld_f, ld_q, (hipStream_t)stream);
+    e = launch_apply_mfma(h, precision, f, Q, B, ld_f, ld_q, (hipStream_t)stream);
   if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return WEFQ_OK;
 }

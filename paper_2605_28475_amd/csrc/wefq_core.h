@@ -28,13 +28,15 @@ struct wefq_core {
   double* d_ent_g = nullptr;
 
   // MFMA path (merged channels sorted by l1)
-  int H = 0, RT = 0, TB = 0, SLOTS = 0;
+  int H = 0, RT = 0, TB = 0, SLOTS = 0, SLOTS64 = 0;   // MFMA geometry (SLOTS: FP32 tiles, SLOTS64: FP64)
   int* d_chan_begin = nullptr;         // L + 2: merged channels of l1 are [begin[l1], begin[l1+1])
   int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
   uint32_t* d_mq = nullptr;            // merged entries: q2 | q3 << 16
   float* d_mg = nullptr;               // merged weights
+  double* d_mg64 = nullptr;            // merged weights, FP64
   float* d_Rt32 = nullptr;             // [NTm][RT][H*H][64]
+  double* d_Rt64 = nullptr;            // [NTm][RT][H*H][64]
   uint16_t* d_Rhi = nullptr;           // [NTm][RT][ceil(H*H/8)][64][8] bf16 bits
   uint16_t* d_Rlo = nullptr;
   int* d_units = nullptr;              // [nunits][3]: l1, q1 begin, count
@@ -75,7 +77,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
 // Kernel launchers (apply.hip).
 hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int64_t B,
                              int64_t ldf, int64_t ldq, hipStream_t s);
-hipError_t launch_apply_mfma(const wefq_core* h, int precision, const float* f, float* Q,
+hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, void* Q,
                              int64_t B, int64_t ldf, int64_t ldq, hipStream_t s);
 hipError_t launch_check(const wefq_core* h, int precision, const void* Q, int64_t B,
                         int64_t ldq, hipStream_t s);

@@ -14,7 +14,7 @@ from paper_2605_28475_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 2e-4}
+TOL = {"fp64": 1e-12, "fp64_naive": 1e-12, "fp32": 1e-5, "bf16x3": 2e-4}
 _cores = {}
 
 
@@ -28,8 +28,8 @@ def gpu_core(model, K, L, gamma=None):
 
 def run(core, c, prec):
     d = dev()
-    if prec == "fp64":
-        return core.apply_Q(torch.tensor(c, device=d)).cpu().numpy()
+    if prec in ("fp64", "fp64_naive"):
+        return core.apply_Q(torch.tensor(c, device=d), precision=prec).cpu().numpy()
     out = core.apply_Q(torch.tensor(c, dtype=torch.float32, device=d), precision=prec)
     return out.cpu().numpy().astype(np.float64)
 
@@ -56,7 +56,7 @@ def test_core_k12_vhs_sampled_channels():
 @pytest.mark.parametrize("K,L,model,gamma,B", [(3, 3, "hs", 1.0, 1), (3, 3, "hs", 1.0, 37),
                                                (4, 4, "vhs", 0.5, 21), (8, 8, "hs", 1.0, 19),
                                                (5, 3, "mm", 0.0, 17), (2, 7, "hs", 1.0, 5)])
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64_naive", "fp32", "bf16x3"])
 def test_apply_matches_oracle(K, L, model, gamma, B, prec):
     say(f"[apply] K={K} L={L} {model} B={B} {prec}")
     core = gpu_core(model, K, L, gamma)
@@ -67,7 +67,7 @@ def test_apply_matches_oracle(K, L, model, gamma, B, prec):
     assert np.all(q[:, invariant_indices(K, L)] == 0.0)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64_naive", "fp32", "bf16x3"])
 def test_unit_maxwellian_is_exact_fixed_point(prec):
     K = L = 4
     core = gpu_core("hs", K, L, 1.0)
@@ -75,7 +75,7 @@ def test_unit_maxwellian_is_exact_fixed_point(prec):
     assert np.all(q == 0.0)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64_naive", "fp32", "bf16x3"])
 def test_cell_result_independent_of_batch(prec):
     K, L = 6, 6
     core = gpu_core("vhs", K, L, 0.5)
@@ -105,7 +105,7 @@ def test_padded_rows_zero_batch_and_errors():
     f = torch.zeros(4 * N + 1, dtype=torch.float32, device=d)
     with pytest.raises(wefq.WefqError):
         core.apply_Q(f[1:].view(4, N))
-    with pytest.raises(wefq.WefqError):
+    with pytest.raises(ValueError):
         core.apply_Q(torch.zeros((2, N), dtype=torch.float64, device=d), precision="fp32")
 
 
@@ -114,7 +114,8 @@ def test_conservation_check_kernel():
     core = gpu_core("hs", K, L, 1.0)
     d = dev()
     c = synth.perturbed_maxwellian(K, L, 300, seed=3)
-    for prec, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16x3", torch.float32)):
+    for prec, dt in (("fp64", torch.float64), ("fp64_naive", torch.float64), ("fp32", torch.float32),
+                     ("bf16x3", torch.float32)):
         q = core.apply_Q(torch.tensor(c, dtype=dt, device=d), precision=prec)
         assert core.check_conservation(q, precision=prec) == 0.0
         q[123, 1] = -2.5
@@ -172,3 +173,17 @@ def test_viscosity_from_gpu_core():
     for K, val in enumerate([1.000000, 1.014851, 1.015879, 1.016006, 1.016028]):
         assert abs(fmu[K] - val) <= 5e-7
     assert abs(fmu[1] - 205 / 202) < 1e-12
+
+
+@pytest.mark.parametrize("K,L", [(12, 12), (16, 16), (16, 4), (3, 16)])
+def test_large_truncations_fp64_tiled_vs_naive(K, L):
+    """Every tile geometry (1, 2 or 4 output states per MFMA column group, two row tiles
+    for NK = 17) against the naive FP64 ordering and the FP32 / BF16x3 paths."""
+    say(f"[large] K={K} L={L}")
+    core = wefq.Core("hs", K, L, device=0)
+    c = synth.perturbed_maxwellian(K, L, 23, seed=K * 100 + L)
+    ref = run(core, c, "fp64_naive")
+    assert rel_err(run(core, c, "fp64"), ref) < 1e-13
+    assert rel_err(run(core, c, "fp32"), ref) < 1e-5
+    assert rel_err(run(core, c, "bf16x3"), ref) < 2e-4
+    core.close()
