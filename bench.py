@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16x3 comparison legs")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of f (known byte count) for counter scaling")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the operator is applied per cell with no exchange between "
@@ -105,6 +107,12 @@ def main():
         core.apply_Q(f32, out=q32)
         check["max"] = core.check_conservation(q32, precision="fp32")
 
+    if args.calibrate_copy:
+        dst = torch.empty_like(f32)
+        dst.copy_(f32)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {f32.numel() * 4} bytes read, {f32.numel() * 4} bytes written")
+        del dst
     log("[bench] warmup")
     for _ in range(args.warmup):
         step()

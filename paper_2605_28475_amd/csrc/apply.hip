@@ -114,7 +114,7 @@ struct MfmaParams {
   const int* chan_begin;   // [L+2]
   const int* slice_off;    // [NTm]
   const int* sptr;         // slices + 1
-  const uint32_t* mq;      // q2 | q3 << 16
+  const uint32_t* mq;      // q2*NK | (q3*NK) << 16 (row offsets of the two gathered states)
   const float* mg;         // merged weights (FP32 / BF16X3)
   const double* mg64;      // merged weights (FP64)
   const float* Rt32;       // [NTm][RT][H*H][64]
@@ -161,15 +161,21 @@ __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
   const int r = lane >> 4, j = lane & 15;
   const int h2 = r >> 1, h3 = r & 1;
   const int cellj = j % TB, slot = j / TB;
-  int k2off[H], k3off[H];
-#pragma unroll
-  for (int a = 0; a < H; ++a) {
-    int k2 = h2 * H + a; k2 = k2 < NK ? k2 : NK - 1;
-    int k3 = h3 * H + a; k3 = k3 < NK ? k3 : NK - 1;
-    k2off[a] = k2 * TB + cellj;
-    k3off[a] = k3 * TB + cellj;
-  }
-  const int rowstride = NK * TB;
+  // lane group r covers k2 in [k2s, k2s+H) and k3 in [k3s, k3s+H): the lower half
+  // starts at 0, the upper at NK-H (for odd NK the middle row is in both halves;
+  // the R tile holds zero for the copy in the upper half), so every gather is a
+  // per-lane base plus a compile-time offset.
+  const int k2s = h2 ? NK - H : 0, k3s = h3 ? NK - H : 0;
+  const T* lane_u = fs + k2s * TB + cellj;
+  const T* lane_w = fs + k3s * TB + cellj;
+  // read-only routing rows: through the constant address space so that
+  // wave-uniform rows are fetched with scalar loads
+  typedef const __attribute__((address_space(4))) uint32_t cu32;
+  typedef const __attribute__((address_space(4))) float cf32;
+  typedef const __attribute__((address_space(4))) double cf64;
+  cu32* mq = (cu32*)p.mq;
+  cf32* mg = (cf32*)p.mg;
+  cf64* mg64 = (cf64*)p.mg64;
   while (true) {
     int u = 0;
     if (lane == 0) u = atomicAdd(&unit_ctr, 1);
@@ -198,18 +204,24 @@ __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
         if (SLOTS == 1) {               // the slice is shared by the whole wave
           e0 = __builtin_amdgcn_readfirstlane(e0);
           e1 = __builtin_amdgcn_readfirstlane(e1);
-          for (int e = e0; e < e1; ++e) {
-            const uint32_t qq = p.mq[e];
-            const T gg = MODE == 2 ? (T)p.mg64[e] : (T)p.mg[e];
-            const T* f2 = fs + (int)(qq & 0xffffu) * rowstride;
-            const T* f3 = fs + (int)(qq >> 16) * rowstride;
-            T uu[H], ww[H];
+          if (e0 < e1) {
+            uint32_t qq = mq[e0];
+            T gg = MODE == 2 ? (T)mg64[e0] : (T)mg[e0];
+            for (int e = e0; e < e1; ++e) {
+              // prefetch the next row (the arrays carry tail slack)
+              const uint32_t qn = mq[e + 1];
+              const T gn = MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1];
+              const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
+              const T* pw = lane_w + (int)(qq >> 16) * TB;
+              T uu[H], ww[H];
 #pragma unroll
-            for (int a = 0; a < H; ++a) { uu[a] = gg * f2[k2off[a]]; ww[a] = f3[k3off[a]]; }
+              for (int a = 0; a < H; ++a) { uu[a] = gg * pu[a * TB]; ww[a] = pw[a * TB]; }
 #pragma unroll
-            for (int a = 0; a < H; ++a)
+              for (int a = 0; a < H; ++a)
 #pragma unroll
-              for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
+                for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
+              qq = qn; gg = gn;
+            }
           }
         } else {
           const int len = e1 - e0;
@@ -222,13 +234,13 @@ __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
           for (int i = 0; i < maxlen; ++i) {
             const bool in = i < len;
             const int e = in ? e0 + i : e0;
-            const uint32_t qq = in ? p.mq[e] : 0u;
-            const T gg = in ? (MODE == 2 ? (T)p.mg64[e] : (T)p.mg[e]) : T(0);
-            const T* f2 = fs + (int)(qq & 0xffffu) * rowstride;
-            const T* f3 = fs + (int)(qq >> 16) * rowstride;
+            const uint32_t qq = in ? mq[e] : 0u;
+            const T gg = in ? (MODE == 2 ? (T)mg64[e] : (T)mg[e]) : T(0);
+            const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
+            const T* pw = lane_w + (int)(qq >> 16) * TB;
             T uu[H], ww[H];
 #pragma unroll
-            for (int a = 0; a < H; ++a) { uu[a] = gg * f2[k2off[a]]; ww[a] = f3[k3off[a]]; }
+            for (int a = 0; a < H; ++a) { uu[a] = gg * pu[a * TB]; ww[a] = pw[a * TB]; }
 #pragma unroll
             for (int a = 0; a < H; ++a)
 #pragma unroll

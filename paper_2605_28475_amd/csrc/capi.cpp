@@ -126,7 +126,9 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
       if (r.q2 > r.q3) continue;
       if (r.q2 < r.q3) g *= 2.0;
     }
-    slices[slice_off[m] + (r.q1 - ch.l1 * ch.l1)].push_back({(uint32_t)r.q2 | ((uint32_t)r.q3 << 16), g});
+    // entries carry the LDS row offsets q*NK of the two gathered states
+    slices[slice_off[m] + (r.q1 - ch.l1 * ch.l1)].push_back(
+        {(uint32_t)(r.q2 * NK) | ((uint32_t)(r.q3 * NK) << 16), g});
     ++ngm;
   }
   std::vector<int> sptr(slices.size() + 1, 0);
@@ -163,9 +165,16 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   h->SLOTS64 = pick_slots(8);
   h->TB = h->SLOTS ? 16 / h->SLOTS : 0;
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;
+  // A-operand value for lane group r at step t: the group's quadrant starts at
+  // 0 (lower half) or NK-H (upper half); a row or column that the upper half
+  // shares with the lower half (odd NK) is counted by the lower half only.
   auto Rval = [&](int m, int k1, int t, int r) -> double {
-    int k2 = (r >> 1) * H + t / H, k3 = (r & 1) * H + t % H;
-    if (k1 >= NK || k2 >= NK || k3 >= NK || t >= HH) return 0.0;
+    if (t >= HH || k1 >= NK) return 0.0;
+    int a = t / H, b = t % H;
+    int h2 = r >> 1, h3 = r & 1;
+    int k2 = (h2 ? NK - H : 0) + a, k3 = (h3 ? NK - H : 0) + b;
+    if (h2 && k2 < H) return 0.0;
+    if (h3 && k3 < H) return 0.0;
     return Rm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3];
   };
   bool want32 = h->precisions & WEFQ_FP32, want16 = h->precisions & WEFQ_BF16X3, want64 = h->precisions & WEFQ_FP64;

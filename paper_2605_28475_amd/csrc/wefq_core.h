@@ -32,7 +32,7 @@ struct wefq_core {
   int* d_chan_begin = nullptr;         // L + 2: merged channels of l1 are [begin[l1], begin[l1+1])
   int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
-  uint32_t* d_mq = nullptr;            // merged entries: q2 | q3 << 16
+  uint32_t* d_mq = nullptr;            // merged entries: q2*NK | (q3*NK) << 16
   float* d_mg = nullptr;               // merged weights
   double* d_mg64 = nullptr;            // merged weights, FP64
   float* d_Rt32 = nullptr;             // [NTm][RT][H*H][64]
