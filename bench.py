@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16x3 comparison legs")
+    ap.add_argument("--workload", choices=["k12", "uneven", "serve"], default="k12",
+                    help="k12: the headline batch; uneven: one persistent launch over a mix of cores; "
+                         "serve: continuous-batching server under Poisson arrivals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of f (known byte count) for counter scaling")
     args = ap.parse_args()
@@ -85,6 +88,12 @@ def main():
     import torch
     import paper_2605_28475_amd as wefq
     from paper_2605_28475_amd import synth
+    if args.workload == "uneven":
+        return bench_uneven(args, torch, wefq, synth)
+    if args.workload == "serve":
+        from paper_2605_28475_amd import serve
+        print(json.dumps(serve.bench(args)), flush=True)
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -183,6 +192,63 @@ def main():
         out["cpu_baseline"] = cpu_baseline(K, L, gamma, c, args.cpu_budget)
     out["host_cpu"] = {"cpu_count": os.cpu_count()}
     core.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_uneven(args, torch, wefq, synth):
+    """20000 cells, K = L drawn from {4, 8, 12, 16}, hard spheres or VHS 0.5, FP32, one
+    persistent graph-captured launch with autotuned tiles, against separate launches."""
+    from paper_2605_28475_amd import autotune
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    cfg = synth.CONFIGS[4]
+    rng = np.random.Generator(np.random.PCG64(cfg["seed"]))
+    total = cfg["cells"]
+    size = rng.choice(np.array(cfg["sizes"]), size=total)
+    model = rng.choice(np.array(["hs", "vhs"]), size=total)
+    segs, flop = [], 0.0
+    for K in cfg["sizes"]:
+        for m in ("hs", "vhs"):
+            B = int(np.sum((size == K) & (model == m)))
+            if B == 0:
+                continue
+            log(f"[uneven] core {m} K=L={K}, {B} cells")
+            core = wefq.Core(m, K, K, gamma=1.0 if m == "hs" else 0.5, device=0, precisions=("fp32",))
+            s, blk, _ = autotune.tune(core, "fp32", cells=min(B, 4096), reps=2)
+            f = torch.tensor(synth.perturbed_maxwellian(K, K, B, seed=cfg["seed"] + 10 * K + (m == "hs")),
+                             dtype=torch.float32, device=dev)
+            segs.append((core, f, torch.empty_like(f), s))
+            flop += core.info["flop_alg_per_cell"] * B
+    best = None
+    for blk in (256, 512):
+        plan = wefq.Plan(segs, precision="fp32", block=blk)
+        plan.launch()
+        ms, _ = time_steps(lambda: plan.launch(), 3, stream, torch)
+        if best is None or np.mean(ms) < best[1]:
+            best = (plan, float(np.mean(ms)), blk)
+    plan, _, blk = best
+    for _ in range(args.warmup):
+        plan.launch()
+    ms, wall = time_steps(lambda: plan.launch(), args.steps, stream, torch)
+    ms_direct, _ = time_steps(lambda: plan.launch(graph=False), args.steps, stream, torch)
+
+    def separate():
+        for core, f, q, _ in segs:
+            core.apply_Q(f, out=q)
+    ms_sep, _ = time_steps(separate, args.steps, stream, torch)
+    t = float(np.mean(ms)) * 1e-3
+    out = {"metric": "Q(f,f) cell-evals/sec, uneven batch in one persistent launch", "value": total / t,
+           "unit": "cells/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": float(np.mean(ms)), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "uneven_20000_K4-16_hs_vhs", "cells": total,
+                      "segments": [{"model": c.model, "K": c.K, "cells": f.shape[0], "slots": s}
+                                   for c, f, _, s in segs], "block": blk, "plan": plan.info},
+           "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
+           "roofline": {"bound": "mfma", "achieved": flop / t / 1e12, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                        "frac": flop / t / 1e12 / PEAK["fp32"], "traffic": None},
+           "graph_ms": float(np.mean(ms)), "direct_ms": float(np.mean(ms_direct)),
+           "separate_launches_ms": float(np.mean(ms_sep))}
     print(json.dumps(out), flush=True)
 
 

@@ -117,6 +117,43 @@ wefq_status wefq_destroy(wefq_handle h);
 
 const char* wefq_last_error(void);
 
+/* Tile shape used by wefq_apply_Q for one precision of a core: slots = output
+ * states sharing the 16 MFMA columns (1, 2 or 4; the cell tile is 16/slots cells
+ * and must fit in LDS), block = threads per workgroup (256 or 512).  Results are
+ * bitwise independent of the shape.  Chosen by the autotuner; not thread-safe
+ * with concurrent applies of the same core. */
+wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32_t block);
+wefq_status wefq_tune_get(wefq_handle h, int32_t precision, int32_t* slots, int32_t* block);
+
+/* ---- uneven batches in one persistent launch (captured in a HIP graph) ---- */
+
+/* One segment of an uneven batch: B cells of core `core` with coefficients f
+ * and outputs Q (device pointers, layout as for wefq_apply_Q).  slots = 0 uses
+ * the core's current tile shape. */
+typedef struct {
+  wefq_handle core;
+  int32_t precision;      /* one precision for the whole plan: FP32, BF16X3 or FP64 */
+  int32_t slots;
+  const void* f;
+  void* Q;
+  int64_t B, ld_f, ld_q;
+} wefq_segment;
+
+/* Build a plan: one work item per (segment, cell tile), largest first, served by a
+ * persistent kernel whose workgroups pull items from a device counter; the counter
+ * reset and the kernel are captured once in a HIP graph.  Per-cell results equal
+ * those of wefq_apply_Q bitwise.  Buffers and cores must outlive the plan; the plan
+ * owns a small device work list.  Synchronizes stream. */
+wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t block, void* stream,
+                             wefq_plan* out);
+/* Replay the captured graph on stream (asynchronous).  Concurrent launches of one
+ * plan race on its counter: serialize them on one stream. */
+wefq_status wefq_plan_launch(wefq_plan p, void* stream);
+/* The same two kernels launched directly, without the graph. */
+wefq_status wefq_plan_launch_direct(wefq_plan p, void* stream);
+wefq_status wefq_plan_info(wefq_plan p, int64_t* work_items, int64_t* lds_bytes, int64_t* grid);
+wefq_status wefq_plan_destroy(wefq_plan p);
+
 /* ---- host-only helpers (no device needed), used to test the host tables ---- */
 
 /* Real-Gaunt COO table (Table 1 order: q3 slowest, q1 fastest, 0-based).  Call

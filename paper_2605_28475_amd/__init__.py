@@ -94,6 +94,16 @@ class Core:
                                                       ctypes.byref(res), _stream_ptr(stream, Q2.device)))
         return res.value
 
+    def tune_set(self, precision, slots, block):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _lib.check(_lib.lib().wefq_tune_set(self._h, prec, int(slots), int(block)))
+
+    def tune_get(self, precision):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        s, b = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib.lib().wefq_tune_get(self._h, prec, ctypes.byref(s), ctypes.byref(b)))
+        return s.value, b.value
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.check(_lib.lib().wefq_destroy(self._h))
@@ -125,3 +135,48 @@ def host_gauss(kind, n, alpha=0.0):
     _lib.check(_lib.lib().wefq_host_gauss(kind, n, alpha, x.ctypes.data_as(ctypes.c_void_p),
                                           w.ctypes.data_as(ctypes.c_void_p)))
     return x, w
+
+
+class Plan:
+    """Uneven batch in one persistent, graph-captured launch (wefq_plan_*).
+
+    segments: list of (core, f, Q) or (core, f, Q, slots) with f, Q CUDA tensors of
+    shape [B_i, N_i].  The plan keeps references to the tensors and cores.
+    """
+
+    def __init__(self, segments, precision="fp32", block=512, stream=None):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        arr = (_lib.Segment * len(segments))()
+        self._keep = []
+        dev = None
+        for i, seg in enumerate(segments):
+            core, f, Q = seg[:3]
+            slots = seg[3] if len(seg) > 3 else 0
+            B = f.shape[0]
+            arr[i] = _lib.Segment(core.handle, prec, int(slots), f.data_ptr(), Q.data_ptr(), B,
+                                  f.stride(0) if B > 1 else f.shape[1], Q.stride(0) if B > 1 else Q.shape[1])
+            self._keep.append((core, f, Q))
+            dev = f.device
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().wefq_plan_create(len(segments), ctypes.cast(arr, ctypes.c_void_p), int(block),
+                                               _stream_ptr(stream, dev), ctypes.byref(h)))
+        self._h = h
+        self.device = dev
+        items, lds, grid = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(_lib.lib().wefq_plan_info(h, ctypes.byref(items), ctypes.byref(lds), ctypes.byref(grid)))
+        self.info = {"work_items": items.value, "lds_bytes": lds.value, "grid": grid.value, "block": block}
+
+    def launch(self, stream=None, graph=True):
+        fn = _lib.lib().wefq_plan_launch if graph else _lib.lib().wefq_plan_launch_direct
+        _lib.check(fn(self._h, _stream_ptr(stream, self.device)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.check(_lib.lib().wefq_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

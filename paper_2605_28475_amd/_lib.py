@@ -26,6 +26,12 @@ class CoreInfo(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("b0", ctypes.c_double)]
 
 
+class Segment(ctypes.Structure):
+    _fields_ = [("core", ctypes.c_void_p), ("precision", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("f", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("B", ctypes.c_int64),
+                ("ld_f", ctypes.c_int64), ("ld_q", ctypes.c_int64)]
+
+
 class WefqError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"wefq {STATUS_NAMES.get(status, status)}: {message}")
@@ -49,6 +55,16 @@ _SIGNATURES = [
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("wefq_host_gauss", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    ("wefq_tune_set", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    ("wefq_tune_get", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
+    ("wefq_plan_create", ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    ("wefq_plan_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("wefq_plan_launch_direct", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("wefq_plan_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]),
+    ("wefq_plan_destroy", ctypes.c_int, [ctypes.c_void_p]),
 ]
 
 

@@ -30,15 +30,9 @@
 
 #include "../../include/wefq.h"
 #include "wefq_core.h"
+#include "apply_tile.h"
 
 namespace wefq {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
-
-__device__ inline bool invariant_row(int q1, int k1) {
-  return (q1 == 0 && k1 <= 1) || (q1 >= 1 && q1 <= 3 && k1 == 0);
-}
 
 struct Fp64Params {
   const double* f;
@@ -104,223 +98,11 @@ hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int
   return hipSuccess;
 }
 
-struct MfmaParams {
-  const void* f;
-  void* Q;
-  int64_t B, ldf, ldq;
-  int NK, NQ, N;
-  int nunits;
-  const int* units;        // [nunits][3]
-  const int* chan_begin;   // [L+2]
-  const int* slice_off;    // [NTm]
-  const int* sptr;         // slices + 1
-  const uint32_t* mq;      // q2*NK | (q3*NK) << 16 (row offsets of the two gathered states)
-  const float* mg;         // merged weights (FP32 / BF16X3)
-  const double* mg64;      // merged weights (FP64)
-  const float* Rt32;       // [NTm][RT][H*H][64]
-  const double* Rt64;      // [NTm][RT][H*H][64]
-  const uint16_t* Rhi;     // [NTm][RT][U][64][8]
-  const uint16_t* Rlo;
-};
-
-// output states per work unit (fewer when NK > 16 needs two accumulator row tiles)
-__host__ __device__ constexpr int gq_for(int H) { return H >= 8 ? 4 : 8; }
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-// MODE 0: FP32 MFMA, 1: split BF16x3 MFMA, 2: FP64 MFMA.
-template <int MODE> struct ModeTraits;
-template <> struct ModeTraits<0> { typedef float T; typedef v4f acc_t; };
-template <> struct ModeTraits<1> { typedef float T; typedef v4f acc_t; };
-template <> struct ModeTraits<2> { typedef double T; typedef v4d acc_t; };
-
 template <int H, int SLOTS, int RT, int MODE>
 __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
-  typedef typename ModeTraits<MODE>::T T;
-  typedef typename ModeTraits<MODE>::acc_t acc_t;
-  constexpr int TB = 16 / SLOTS;
-  constexpr int HH = H * H;
-  constexpr int U = (HH + 7) / 8;
-  constexpr int GQ = gq_for(H);
-  constexpr int NP = GQ / SLOTS > 0 ? GQ / SLOTS : 1;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* fs = reinterpret_cast<T*>(lds_raw);
   __shared__ int unit_ctr;
-  const T* f = static_cast<const T*>(p.f);
-  T* Qo = static_cast<T*>(p.Q);
-  const int NK = p.NK;
-  const int64_t cell0 = (int64_t)blockIdx.x * TB;
-  // stage the coefficient tile: fs[n * TB + cell]
-  for (int idx = threadIdx.x; idx < TB * p.N; idx += blockDim.x) {
-    const int cl = idx / p.N, n = idx - cl * p.N;
-    const int64_t cell = cell0 + cl;
-    fs[n * TB + cl] = (cell < p.B) ? f[cell * p.ldf + n] : T(0);
-  }
-  if (threadIdx.x == 0) unit_ctr = 0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int r = lane >> 4, j = lane & 15;
-  const int h2 = r >> 1, h3 = r & 1;
-  const int cellj = j % TB, slot = j / TB;
-  // lane group r covers k2 in [k2s, k2s+H) and k3 in [k3s, k3s+H): the lower half
-  // starts at 0, the upper at NK-H (for odd NK the middle row is in both halves;
-  // the R tile holds zero for the copy in the upper half), so every gather is a
-  // per-lane base plus a compile-time offset.
-  const int k2s = h2 ? NK - H : 0, k3s = h3 ? NK - H : 0;
-  const T* lane_u = fs + k2s * TB + cellj;
-  const T* lane_w = fs + k3s * TB + cellj;
-  // read-only routing rows: through the constant address space so that
-  // wave-uniform rows are fetched with scalar loads
-  typedef const __attribute__((address_space(4))) uint32_t cu32;
-  typedef const __attribute__((address_space(4))) float cf32;
-  typedef const __attribute__((address_space(4))) double cf64;
-  cu32* mq = (cu32*)p.mq;
-  cf32* mg = (cf32*)p.mg;
-  cf64* mg64 = (cf64*)p.mg64;
-  while (true) {
-    int u = 0;
-    if (lane == 0) u = atomicAdd(&unit_ctr, 1);
-    u = __shfl(u, 0);
-    if (u >= p.nunits) break;
-    const int l1 = p.units[3 * u], qb = p.units[3 * u + 1], nq = p.units[3 * u + 2];
-    acc_t acc[NP][RT];
-#pragma unroll
-    for (int gi = 0; gi < NP; ++gi)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[gi][rt] = (acc_t){0, 0, 0, 0};
-    const int cb = p.chan_begin[l1], ce = p.chan_begin[l1 + 1];
-    for (int ct = cb; ct < ce; ++ct) {
-      const int soff = p.slice_off[ct] - l1 * l1;
-#pragma unroll
-      for (int gi = 0; gi < NP; ++gi) {
-        if (gi * SLOTS >= nq) break;
-        const int qi = gi * SLOTS + slot;
-        const bool qvalid = qi < nq;
-        const int s = soff + qb + (qvalid ? qi : 0);
-        int e0 = p.sptr[s], e1 = p.sptr[s + 1];
-        if (!qvalid) e1 = e0;
-        T phi[U * 8];
-#pragma unroll
-        for (int t = 0; t < U * 8; ++t) phi[t] = T(0);
-        if (SLOTS == 1) {               // the slice is shared by the whole wave
-          e0 = __builtin_amdgcn_readfirstlane(e0);
-          e1 = __builtin_amdgcn_readfirstlane(e1);
-          if (e0 < e1) {
-            uint32_t qq = mq[e0];
-            T gg = MODE == 2 ? (T)mg64[e0] : (T)mg[e0];
-            for (int e = e0; e < e1; ++e) {
-              // prefetch the next row (the arrays carry tail slack)
-              const uint32_t qn = mq[e + 1];
-              const T gn = MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1];
-              const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
-              const T* pw = lane_w + (int)(qq >> 16) * TB;
-              T uu[H], ww[H];
-#pragma unroll
-              for (int a = 0; a < H; ++a) { uu[a] = gg * pu[a * TB]; ww[a] = pw[a * TB]; }
-#pragma unroll
-              for (int a = 0; a < H; ++a)
-#pragma unroll
-                for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
-              qq = qn; gg = gn;
-            }
-          }
-        } else {
-          const int len = e1 - e0;
-          int maxlen = len;
-#pragma unroll
-          for (int off = TB; off < 16; off <<= 1) {
-            const int o = __shfl_xor(maxlen, off);
-            maxlen = maxlen > o ? maxlen : o;
-          }
-          for (int i = 0; i < maxlen; ++i) {
-            const bool in = i < len;
-            const int e = in ? e0 + i : e0;
-            const uint32_t qq = in ? mq[e] : 0u;
-            const T gg = in ? (MODE == 2 ? (T)mg64[e] : (T)mg[e]) : T(0);
-            const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
-            const T* pw = lane_w + (int)(qq >> 16) * TB;
-            T uu[H], ww[H];
-#pragma unroll
-            for (int a = 0; a < H; ++a) { uu[a] = gg * pu[a * TB]; ww[a] = pw[a * TB]; }
-#pragma unroll
-            for (int a = 0; a < H; ++a)
-#pragma unroll
-              for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
-          }
-        }
-        if constexpr (MODE == 0) {
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            const float* At = p.Rt32 + ((int64_t)(ct * RT + rt) * HH) * 64 + lane;
-#pragma unroll
-            for (int t0 = 0; t0 < HH; t0 += 8) {
-              float av[8];
-#pragma unroll
-              for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0f;
-              __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-              for (int t = 0; t < 8; ++t)
-                if (t0 + t < HH)
-                  acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], phi[t0 + t], acc[gi][rt], 0, 0, 0);
-            }
-          }
-        } else if constexpr (MODE == 2) {
-#pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            const double* At = p.Rt64 + ((int64_t)(ct * RT + rt) * HH) * 64 + lane;
-#pragma unroll
-            for (int t0 = 0; t0 < HH; t0 += 8) {
-              double av[8];
-#pragma unroll
-              for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0;
-              __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-              for (int t = 0; t < 8; ++t)
-                if (t0 + t < HH)
-                  acc[gi][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], phi[t0 + t], acc[gi][rt], 0, 0, 0);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int uu8 = 0; uu8 < U; ++uu8) {
-            v8bf bh, bl;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const float x = phi[uu8 * 8 + e];
-              const __bf16 xh = (__bf16)x;
-              bh[e] = xh;
-              bl[e] = (__bf16)(x - (float)xh);
-            }
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-              const int64_t off = (((int64_t)(ct * RT + rt) * U + uu8) * 64 + lane) * 8;
-              const v8bf ah = *reinterpret_cast<const v8bf*>(p.Rhi + off);
-              const v8bf al = *reinterpret_cast<const v8bf*>(p.Rlo + off);
-              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[gi][rt], 0, 0, 0);
-              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[gi][rt], 0, 0, 0);
-              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[gi][rt], 0, 0, 0);
-            }
-          }
-        }
-      }
-    }
-    // write the accumulator tiles: column lane%16; output register i holds row
-    // 4*(lane/16)+i for the FP32 and BF16 forms and row lane/16+4*i for the FP64 form
-    const int64_t cell = cell0 + cellj;
-#pragma unroll
-    for (int gi = 0; gi < NP; ++gi) {
-      const int qi = gi * SLOTS + slot;
-      if (qi >= nq || cell >= p.B) continue;
-      const int q1 = qb + qi;
-      T* dst = Qo + cell * p.ldq + (int64_t)q1 * NK;
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int k1 = rt * 16 + (MODE == 2 ? r + 4 * i : 4 * r + i);
-          if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? T(0) : (T)acc[gi][rt][i];
-        }
-    }
-  }
+  mfma_tile<H, SLOTS, RT, MODE>(p, (int64_t)blockIdx.x, lds_raw, &unit_ctr);
 }
 
 template <int H, int SLOTS, int RT, int MODE>

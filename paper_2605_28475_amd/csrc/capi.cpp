@@ -155,6 +155,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess || dev_lds <= 0)
     dev_lds = 65536;
   const size_t limit = (size_t)std::min(dev_lds, 163840) - 512;
+  h->lds_limit = (int)limit;
   // output states sharing the 16 MFMA columns, so that a tile of 16/SLOTS cells fits in LDS
   auto pick_slots = [&](size_t elem) {
     for (int sl : {1, 2, 4})
@@ -233,7 +234,8 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   }
   std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
   std::vector<int> uarr;
-  for (auto& u : units) { uarr.push_back(u.l1); uarr.push_back(u.qb); uarr.push_back(u.nq); }
+  h->tile_cost = 0.0;
+  for (auto& u : units) { uarr.push_back(u.l1); uarr.push_back(u.qb); uarr.push_back(u.nq); h->tile_cost += u.cost; }
   h->nunits = (int)units.size();
   if (!upload(h, h->d_units, uarr, s) || !upload(h, h->d_chan_begin, chan_begin, s) ||
       !upload(h, h->d_slice_off, slice_off, s) || !upload(h, h->d_sptr, sptr, s) ||
@@ -386,6 +388,27 @@ wefq_status wefq_check_conservation(wefq_handle h, int32_t precision, const void
   double m = 0.0;
   for (double v : part) m = (v > m || v != v) ? v : m;
   *max_abs = m;
+  return WEFQ_OK;
+}
+
+wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32_t block) {
+  if (!h) return fail(WEFQ_EINVAL, "null handle");
+  if (precision != WEFQ_FP64 && precision != WEFQ_FP32 && precision != WEFQ_BF16X3)
+    return fail(WEFQ_EINVAL, "tile shapes exist for FP64, FP32 and BF16X3");
+  if (slots != 1 && slots != 2 && slots != 4) return fail(WEFQ_EINVAL, "slots must be 1, 2 or 4");
+  if (block != 256 && block != 512) return fail(WEFQ_EINVAL, "block must be 256 or 512");
+  const size_t elem = precision == WEFQ_FP64 ? 8 : 4;
+  if ((size_t)h->N * (16 / slots) * elem > (size_t)h->lds_limit)
+    return fail(WEFQ_EUNSUPPORTED, "tile of 16/slots cells does not fit in LDS");
+  if (precision == WEFQ_FP64) h->SLOTS64 = slots; else h->SLOTS = slots;
+  h->block = block;
+  return WEFQ_OK;
+}
+
+wefq_status wefq_tune_get(wefq_handle h, int32_t precision, int32_t* slots, int32_t* block) {
+  if (!h || !slots || !block) return fail(WEFQ_EINVAL, "null argument");
+  *slots = precision == WEFQ_FP64 ? h->SLOTS64 : h->SLOTS;
+  *block = h->block;
   return WEFQ_OK;
 }
 

@@ -42,6 +42,8 @@ struct wefq_core {
   int* d_units = nullptr;              // [nunits][3]: l1, q1 begin, count
   int nunits = 0;
   int GQ = 0;                          // q1 per unit
+  double tile_cost = 0.0;              // estimated cost of one full 16-cell tile (scheduling only)
+  int lds_limit = 0;                   // usable LDS bytes per workgroup
   int block = 512;                     // threads per workgroup of the MFMA kernel
 
   // conservation check scratch

@@ -1,0 +1,91 @@
+"""Uneven batches in one persistent, graph-captured launch; autotuner."""
+import numpy as np
+import pytest
+
+from gpu_common import dev, say, torch
+
+import paper_2605_28475_amd as wefq
+from paper_2605_28475_amd import autotune, synth
+
+pytestmark = pytest.mark.gpu
+
+_cores = {}
+
+
+def core(model, K, gamma=None):
+    key = (model, K, gamma)
+    if key not in _cores:
+        say(f"[build] {key}")
+        _cores[key] = wefq.Core(model, K, K, gamma=gamma, device=0)
+    return _cores[key]
+
+
+def segments(prec, specs):
+    d = dev()
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    out = []
+    for i, (model, K, gamma, B) in enumerate(specs):
+        c = core(model, K, gamma)
+        f = torch.tensor(synth.perturbed_maxwellian(K, K, B, seed=1000 + i), dtype=dt, device=d)
+        out.append((c, f, torch.empty_like(f)))
+    return out
+
+
+MIX = [("hs", 4, None, 37), ("vhs", 8, 0.5, 1), ("hs", 12, None, 130), ("vhs", 16, 0.5, 9),
+       ("mm", 3, None, 64), ("hs", 16, None, 17), ("vhs", 12, 0.5, 33), ("hs", 8, None, 5)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_plan_matches_single_segment_applies(prec):
+    say(f"[plan] {prec}")
+    segs = segments(prec, MIX if prec == "fp32" else MIX[:4])
+    refs = [c.apply_Q(f, precision=prec).clone() for c, f, _ in segs]
+    plan = wefq.Plan(segs, precision=prec)
+    assert plan.info["work_items"] > 0
+    for replay in range(3):
+        for _, _, q in segs:
+            q.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for (c, f, q), r in zip(segs, refs):
+            assert torch.equal(q, r), f"replay {replay} K={c.K}"
+        # unrelated eager work between replays
+        torch.ones(1000, device=dev()).sum().item()
+    for _, _, q in segs:
+        q.zero_()
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    for (c, f, q), r in zip(segs, refs):
+        assert torch.equal(q, r)
+    plan.close()
+
+
+def test_plan_tile_shape_override_keeps_results():
+    segs = segments("fp32", [("hs", 4, None, 40), ("vhs", 8, 0.5, 23)])
+    refs = [c.apply_Q(f).clone() for c, f, _ in segs]
+    plan = wefq.Plan([(c, f, q, 4) for c, f, q in segs], precision="fp32", block=256)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (_, _, q), r in zip(segs, refs):
+        assert torch.equal(q, r)
+    plan.close()
+
+
+def test_autotuner_picks_valid_shape_and_keeps_results():
+    c = core("vhs", 8, 0.5)
+    f = torch.tensor(synth.perturbed_maxwellian(8, 8, 300, seed=4), dtype=torch.float32, device=dev())
+    before = c.apply_Q(f).clone()
+    s, b, timings = autotune.tune(c, "fp32", cells=256, reps=2, use_cache=False)
+    assert (s, b) == c.tune_get("fp32") and len(timings) >= 2
+    assert torch.equal(c.apply_Q(f), before)
+    c.tune_set("fp32", 1, 512)
+
+
+def test_plan_rejects_bad_segments():
+    c = core("hs", 4)
+    f = torch.zeros((4, c.N), dtype=torch.float32, device=dev())
+    with pytest.raises(wefq.WefqError):
+        wefq.Plan([(c, f, torch.empty_like(f))], precision="fp32", block=300)
+    with pytest.raises(wefq.WefqError):
+        wefq.Plan([(c, f, torch.empty_like(f), 3)], precision="fp32")
