@@ -99,8 +99,8 @@ wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count);
 
 /* Q = Q(f, f) for B independent cells (eq. full_discrete_sum, Section 4.5).
  * f and Q are device pointers, row-major [B][ld_f] / [B][ld_q], ld >= N,
- * double for WEFQ_FP64 / WEFQ_FP64_NAIVE and float otherwise, 16-byte aligned,
- * not aliasing.  Requesting WEFQ_FP64_NAIVE needs the WEFQ_FP64 tables.
+ * double for WEFQ_FP64 / WEFQ_FP64_NAIVE and float otherwise, aligned to the
+ * element size, not aliasing.  Requesting WEFQ_FP64_NAIVE needs the WEFQ_FP64 tables.
  * Q is overwritten (not accumulated).  B == 0 is a no-op.  Asynchronous on
  * stream; allocates nothing.  The mass, momentum and energy rows of Q are
  * exactly 0 for every precision.  NaN/Inf in f propagate elsewhere. */

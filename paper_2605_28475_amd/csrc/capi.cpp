@@ -348,7 +348,9 @@ static wefq_status check_batch(wefq_handle h, int32_t precision, const void* a, 
   if (B == 0) return WEFQ_OK;
   if (!a) return fail(WEFQ_EINVAL, "null input pointer");
   if (lda < h->N || ldb < h->N) return fail(WEFQ_EINVAL, "leading dimension smaller than N");
-  if (((uintptr_t)a & 15) || (b && ((uintptr_t)b & 15))) return fail(WEFQ_EINVAL, "pointers must be 16-byte aligned");
+  const uintptr_t align = (precision == WEFQ_FP64 || precision == WEFQ_FP64_NAIVE) ? 7 : 3;
+  if (((uintptr_t)a & align) || (b && ((uintptr_t)b & align)))
+    return fail(WEFQ_EINVAL, "pointers must be aligned to the element size");
   return WEFQ_OK;
 }
 

@@ -144,7 +144,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     if (g.B < 0) return plan_fail(WEFQ_EINVAL, "negative segment size");
     if (g.B > 0 && (!g.f || !g.Q)) return plan_fail(WEFQ_EINVAL, "null segment buffer");
     if (g.ld_f < h->N || g.ld_q < h->N) return plan_fail(WEFQ_EINVAL, "leading dimension smaller than N");
-    if (((uintptr_t)g.f & 15) || ((uintptr_t)g.Q & 15)) return plan_fail(WEFQ_EINVAL, "buffers must be 16-byte aligned");
+    if (((uintptr_t)g.f | (uintptr_t)g.Q) & (elem - 1)) return plan_fail(WEFQ_EINVAL, "buffers must be aligned to the element size");
     int slots = g.slots ? g.slots : (mode == 2 ? h->SLOTS64 : h->SLOTS);
     if (slots != 1 && slots != 2 && slots != 4) return plan_fail(WEFQ_EINVAL, "slots must be 0, 1, 2 or 4");
     const int TB = 16 / slots;

@@ -102,9 +102,14 @@ def test_padded_rows_zero_batch_and_errors():
     assert np.all(q[:, N:] == 7.0)
     empty = torch.empty((0, N), dtype=torch.float32, device=d)
     assert core.apply_Q(empty).shape == (0, N)
-    f = torch.zeros(4 * N + 1, dtype=torch.float32, device=d)
-    with pytest.raises(wefq.WefqError):
-        core.apply_Q(f[1:].view(4, N))
+    f = torch.zeros(8 * N + 2, dtype=torch.float32, device=d)
+    q = torch.zeros(8 * N + 2, dtype=torch.float32, device=d)
+    core.apply_Q(f[1:1 + 4 * N].view(4, N), out=q[1:1 + 4 * N].view(4, N))   # 4-byte aligned is enough
+    import ctypes
+    from paper_2605_28475_amd import _lib
+    st = _lib.lib().wefq_apply_Q(core.handle, _lib.FP32, ctypes.c_void_p(f.data_ptr() + 2),
+                                 ctypes.c_void_p(q.data_ptr()), 4, N, N, None)   # 2-byte aligned input
+    assert st == _lib.WEFQ_EINVAL
     with pytest.raises(ValueError):
         core.apply_Q(torch.zeros((2, N), dtype=torch.float64, device=d), precision="fp32")
 
