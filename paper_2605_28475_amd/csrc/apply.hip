@@ -155,6 +155,7 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
   p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mg = h->d_mg; p.mg64 = h->d_mg64;
   p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
+  p.R16_32 = h->d_R16_32; p.R16_64 = h->d_R16_64;
   const int mode = precision == WEFQ_FP64 ? 2 : (precision == WEFQ_BF16X3 ? 1 : 0);
   const int slots = mode == 2 ? h->SLOTS64 : h->SLOTS;
   if (slots == 0) return hipErrorInvalidValue;

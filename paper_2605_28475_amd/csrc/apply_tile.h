@@ -29,8 +29,10 @@ struct MfmaParams {
   const double* mg64;      // merged weights (FP64)
   const float* Rt32;       // [NTm][RT][H*H][64]
   const double* Rt64;      // [NTm][RT][H*H][64]
-  const uint16_t* Rhi;     // [NTm][RT][U][64][8]
+  const uint16_t* Rhi;     // [NTm][U][64][8]
   const uint16_t* Rlo;
+  const float* R16_32;     // NK = 17 only: row k1 = 16 of R per lane group, [NTm][4][H*H]
+  const double* R16_64;
 };
 
 // output states per work unit (fewer when NK > 16 needs two accumulator row tiles)
@@ -93,11 +95,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
     u = __shfl(u, 0);
     if (u >= p.nunits) break;
     const int l1 = p.units[3 * u], qb = p.units[3 * u + 1], nq = p.units[3 * u + 2];
-    acc_t acc[NP][RT];
+    // RT == 2 marks NK = 17: rows 0..15 on MFMA, row 16 as a VALU dot product
+    acc_t acc[NP][1];
+    T acc16[NP];
 #pragma unroll
-    for (int gi = 0; gi < NP; ++gi)
-#pragma unroll
-      for (int rt = 0; rt < RT; ++rt) acc[gi][rt] = (acc_t){0, 0, 0, 0};
+    for (int gi = 0; gi < NP; ++gi) { acc[gi][0] = (acc_t){0, 0, 0, 0}; acc16[gi] = T(0); }
     const int cb = p.chan_begin[l1], ce = p.chan_begin[l1 + 1];
     for (int ct = cb; ct < ce; ++ct) {
       const int soff = p.slice_off[ct] - l1 * l1;
@@ -160,8 +162,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
         }
         if constexpr (MODE == 0) {
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            const float* At = p.Rt32 + ((int64_t)(ct * RT + rt) * HH) * 64 + lane;
+          for (int rt = 0; rt < 1; ++rt) {
+            const float* At = p.Rt32 + ((int64_t)ct * HH) * 64 + lane;
 #pragma unroll
             for (int t0 = 0; t0 < HH; t0 += 8) {
               float av[8];
@@ -176,8 +178,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
           }
         } else if constexpr (MODE == 2) {
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) {
-            const double* At = p.Rt64 + ((int64_t)(ct * RT + rt) * HH) * 64 + lane;
+          for (int rt = 0; rt < 1; ++rt) {
+            const double* At = p.Rt64 + ((int64_t)ct * HH) * 64 + lane;
 #pragma unroll
             for (int t0 = 0; t0 < HH; t0 += 8) {
               double av[8];
@@ -202,8 +204,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
               bl[e] = (__bf16)(x - (float)xh);
             }
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt) {
-              const int64_t off = (((int64_t)(ct * RT + rt) * U + uu8) * 64 + lane) * 8;
+            for (int rt = 0; rt < 1; ++rt) {
+              const int64_t off = (((int64_t)ct * U + uu8) * 64 + lane) * 8;
               const v8bf ah = *reinterpret_cast<const v8bf*>(p.Rhi + off);
               const v8bf al = *reinterpret_cast<const v8bf*>(p.Rlo + off);
               acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[gi][rt], 0, 0, 0);
@@ -211,6 +213,23 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
               acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[gi][rt], 0, 0, 0);
             }
           }
+        }
+        if constexpr (RT == 2) {
+          // row k1 = 16: partial dot product over this lane group's quadrant, then
+          // the four lane groups of a column (lanes j, j+16, j+32, j+48) are summed
+          T part = T(0);
+          if constexpr (MODE == 2) {
+            const double* r16 = p.R16_64 + ((int64_t)ct * 4 + r) * HH;
+#pragma unroll
+            for (int t = 0; t < HH; ++t) part = fma((T)r16[t], phi[t], part);
+          } else {
+            const float* r16 = p.R16_32 + ((int64_t)ct * 4 + r) * HH;
+#pragma unroll
+            for (int t = 0; t < HH; ++t) part = fma((T)r16[t], phi[t], part);
+          }
+          part += __shfl_xor(part, 16);
+          part += __shfl_xor(part, 32);
+          acc16[gi] += part;
         }
       }
     }
@@ -224,12 +243,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
       const int q1 = qb + qi;
       T* dst = Qo + cell * p.ldq + (int64_t)q1 * NK;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int k1 = rt * 16 + (MODE == 2 ? r + 4 * i : 4 * r + i);
-          if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? T(0) : (T)acc[gi][rt][i];
-        }
+      for (int i = 0; i < 4; ++i) {
+        const int k1 = MODE == 2 ? r + 4 * i : 4 * r + i;
+        if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? T(0) : (T)acc[gi][0][i];
+      }
+      if (RT == 2 && r == 0) dst[16] = acc16[gi];
     }
   }
 }

@@ -165,7 +165,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   h->SLOTS = pick_slots(4);
   h->SLOTS64 = pick_slots(8);
   h->TB = h->SLOTS ? 16 / h->SLOTS : 0;
-  const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;
+  const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;   // RT == 2: NK = 17
   // A-operand value for lane group r at step t: the group's quadrant starts at
   // 0 (lower half) or NK-H (upper half); a row or column that the upper half
   // shares with the lower half (odd NK) is counted by the lower half only.
@@ -183,37 +183,47 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     set_error("coefficient tile does not fit in LDS for this truncation");
     return false;
   }
-  if (want64) {
-    std::vector<double> t64((size_t)NTm * RT * HH * 64);
+  // NK = 17: row k1 = 16 of every merged channel per lane group, for the VALU dot product
+  std::vector<double> r16;
+  if (RT == 2) {
+    r16.assign((size_t)NTm * 4 * HH, 0.0);
     for (int m = 0; m < NTm; ++m)
-      for (int rt = 0; rt < RT; ++rt)
-        for (int t = 0; t < HH; ++t)
-          for (int ln = 0; ln < 64; ++ln)
-            t64[(((size_t)m * RT + rt) * HH + t) * 64 + ln] = Rval(m, rt * 16 + (ln & 15), t, ln >> 4);
+      for (int r = 0; r < 4; ++r)
+        for (int t = 0; t < HH; ++t) r16[((size_t)m * 4 + r) * HH + t] = Rval(m, 16, t, r);
+  }
+  if (want64) {
+    std::vector<double> t64((size_t)NTm * HH * 64);
+    for (int m = 0; m < NTm; ++m)
+      for (int t = 0; t < HH; ++t)
+        for (int ln = 0; ln < 64; ++ln)
+          t64[((size_t)m * HH + t) * 64 + ln] = Rval(m, ln & 15, t, ln >> 4);
     if (!upload(h, h->d_Rt64, t64, s) || !upload(h, h->d_mg64, mg64, s)) return false;
+    if (RT == 2 && !upload(h, h->d_R16_64, r16, s)) return false;
+  }
+  if ((want32 || want16) && RT == 2) {
+    std::vector<float> r16f(r16.begin(), r16.end());
+    if (!upload(h, h->d_R16_32, r16f, s)) return false;
   }
   if (want32) {
-    std::vector<float> t32((size_t)NTm * RT * HH * 64);
+    std::vector<float> t32((size_t)NTm * HH * 64);
     for (int m = 0; m < NTm; ++m)
-      for (int rt = 0; rt < RT; ++rt)
-        for (int t = 0; t < HH; ++t)
-          for (int ln = 0; ln < 64; ++ln)
-            t32[(((size_t)m * RT + rt) * HH + t) * 64 + ln] = (float)Rval(m, rt * 16 + (ln & 15), t, ln >> 4);
+      for (int t = 0; t < HH; ++t)
+        for (int ln = 0; ln < 64; ++ln)
+          t32[((size_t)m * HH + t) * 64 + ln] = (float)Rval(m, ln & 15, t, ln >> 4);
     if (!upload(h, h->d_Rt32, t32, s)) return false;
   }
   if (want16) {
-    std::vector<uint16_t> hi((size_t)NTm * RT * UU * 64 * 8), lo(hi.size());
+    std::vector<uint16_t> hi((size_t)NTm * UU * 64 * 8), lo(hi.size());
     for (int m = 0; m < NTm; ++m)
-      for (int rt = 0; rt < RT; ++rt)
-        for (int u = 0; u < UU; ++u)
-          for (int ln = 0; ln < 64; ++ln)
-            for (int e = 0; e < 8; ++e) {
-              double v = Rval(m, rt * 16 + (ln & 15), u * 8 + e, ln >> 4);
-              uint16_t bh = bf16_bits((float)v);
-              uint16_t bl = bf16_bits((float)(v - (double)bf16_to_float(bh)));
-              size_t idx = ((((size_t)m * RT + rt) * UU + u) * 64 + ln) * 8 + e;
-              hi[idx] = bh; lo[idx] = bl;
-            }
+      for (int u = 0; u < UU; ++u)
+        for (int ln = 0; ln < 64; ++ln)
+          for (int e = 0; e < 8; ++e) {
+            double v = Rval(m, ln & 15, u * 8 + e, ln >> 4);
+            uint16_t bh = bf16_bits((float)v);
+            uint16_t bl = bf16_bits((float)(v - (double)bf16_to_float(bh)));
+            size_t idx = (((size_t)m * UU + u) * 64 + ln) * 8 + e;
+            hi[idx] = bh; lo[idx] = bl;
+          }
     if (!upload(h, h->d_Rhi, hi, s) || !upload(h, h->d_Rlo, lo, s)) return false;
   }
   // work units: (l1, first q1, count), largest estimated cost first

@@ -159,6 +159,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
     p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mg = h->d_mg; p.mg64 = h->d_mg64;
     p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
+    p.R16_32 = h->d_R16_32; p.R16_64 = h->d_R16_64;
     d.H = h->H; d.SLOTS = slots; d.RT = h->RT;
     const int64_t ntiles = (g.B + TB - 1) / TB;
     if (ntiles >= (1LL << 40)) return plan_fail(WEFQ_EINVAL, "segment too large");

@@ -29,15 +29,18 @@ struct wefq_core {
 
   // MFMA path (merged channels sorted by l1)
   int H = 0, RT = 0, TB = 0, SLOTS = 0, SLOTS64 = 0;   // MFMA geometry (SLOTS: FP32 tiles, SLOTS64: FP64)
+                                       // RT == 2 marks NK = 17 (row 16 on the VALU)
   int* d_chan_begin = nullptr;         // L + 2: merged channels of l1 are [begin[l1], begin[l1+1])
   int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
   uint32_t* d_mq = nullptr;            // merged entries: q2*NK | (q3*NK) << 16
   float* d_mg = nullptr;               // merged weights
   double* d_mg64 = nullptr;            // merged weights, FP64
-  float* d_Rt32 = nullptr;             // [NTm][RT][H*H][64]
-  double* d_Rt64 = nullptr;            // [NTm][RT][H*H][64]
-  uint16_t* d_Rhi = nullptr;           // [NTm][RT][ceil(H*H/8)][64][8] bf16 bits
+  float* d_Rt32 = nullptr;             // [NTm][H*H][64]  (rows k1 < 16)
+  double* d_Rt64 = nullptr;            // [NTm][H*H][64]
+  float* d_R16_32 = nullptr;           // NK = 17: row k1 = 16, [NTm][4][H*H]
+  double* d_R16_64 = nullptr;
+  uint16_t* d_Rhi = nullptr;           // [NTm][ceil(H*H/8)][64][8] bf16 bits
   uint16_t* d_Rlo = nullptr;
   int* d_units = nullptr;              // [nunits][3]: l1, q1 begin, count
   int nunits = 0;

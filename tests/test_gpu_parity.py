@@ -192,3 +192,18 @@ def test_large_truncations_fp64_tiled_vs_naive(K, L):
     assert rel_err(run(core, c, "fp32"), ref) < 1e-5
     assert rel_err(run(core, c, "bf16x3"), ref) < 2e-4
     core.close()
+
+
+@pytest.mark.parametrize("K,L,model,gamma", [(12, 12, "vhs", 0.5), (16, 16, "hs", 1.0), (5, 9, "mm", 0.0)])
+def test_rotation_equivariance_on_gpu(K, L, model, gamma):
+    """Q(D c) = D Q(c) through the GPU path at every precision (no reference values needed)."""
+    from rotation import random_rotation, rotate, wigner_blocks
+    say(f"[rotation] K={K} L={L} {model}")
+    core = gpu_core(model, K, L, gamma)
+    blocks = wigner_blocks(L, random_rotation(K + L))
+    c = synth.perturbed_maxwellian(K, L, 6, seed=77)
+    cr = rotate(c, K, L, blocks)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5), ("bf16x3", 4e-4)):
+        q = run(core, c, prec)
+        qr = run(core, cr, prec)
+        assert rel_err(qr, rotate(q, K, L, blocks)) < tol, prec

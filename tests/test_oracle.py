@@ -263,3 +263,19 @@ def test_galilean_shift_table5():
     assert norms[0.0] < 1e-14
     assert abs(math.log(norms[0.3] / norms[0.1]) / math.log(3) - 8) < 0.05
     assert abs(math.log(norms[0.6] / norms[0.3]) / math.log(2) - 8) < 0.1
+
+
+def test_rotation_equivariance_of_factorized_sum():
+    """Q(D c) = D Q(c) for a random rotation (isotropic kernel, SO(3) covariance)."""
+    from rotation import random_rotation, rotate, wigner_blocks
+    K, L = 3, 4
+    R = core_zeroed(K, L, 0.5)
+    T = coo(L)
+    blocks = wigner_blocks(L, random_rotation(5))
+    for D in blocks:
+        assert np.abs(D @ D.T - np.eye(len(D))).max() < 1e-13
+    c = np.zeros((2, basis.num_modes(K, L))); c[:, 0] = 1.0
+    c += 0.05 * np.random.default_rng(2).standard_normal(c.shape)
+    Qc = apply.apply_q(R, T, c, K)
+    Qr = apply.apply_q(R, T, rotate(c, K, L, blocks), K)
+    assert np.abs(Qr - rotate(Qc, K, L, blocks)).max() < 1e-14 * np.abs(Qc).max() * 10
