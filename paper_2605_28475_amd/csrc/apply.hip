@@ -153,7 +153,8 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   p.f = f; p.Q = Q; p.B = B; p.ldf = ldf; p.ldq = ldq;
   p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
   p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
-  p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mg = h->d_mg; p.mg64 = h->d_mg64;
+  p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
+  p.mg = h->d_mg; p.mg64 = h->d_mg64;
   p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
   p.R16_32 = h->d_R16_32; p.R16_64 = h->d_R16_64;
   const int mode = precision == WEFQ_FP64 ? 2 : (precision == WEFQ_BF16X3 ? 1 : 0);
@@ -161,7 +162,7 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   if (slots == 0) return hipErrorInvalidValue;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
-  const size_t lds = (size_t)h->N * TB * (mode == 2 ? 8 : 4);
+  const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   switch (h->H) {
     case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
     case 2: return launch_mfma_h<2>(p, mode, slots, h->RT, ntiles, h->block, lds, s);

@@ -24,7 +24,8 @@ struct MfmaParams {
   const int* chan_begin;   // [L+2]
   const int* slice_off;    // [NTm]
   const int* sptr;         // slices + 1
-  const uint32_t* mq;      // q2*NK | (q3*NK) << 16 (row offsets of the two gathered states)
+  const uint32_t* mq;      // q2*NKp | (q3*NKp) << 16: LDS row offsets of the two gathered states
+  const uint32_t* mq_pad;  // the same with the padded row pitch (16-cell tiles with a pad row)
   const float* mg;         // merged weights (FP32 / BF16X3)
   const double* mg64;      // merged weights (FP64)
   const float* Rt32;       // [NTm][RT][H*H][64]
@@ -45,6 +46,12 @@ template <> struct ModeTraits<0> { typedef float T; typedef v4f acc_t; };
 template <> struct ModeTraits<1> { typedef float T; typedef v4f acc_t; };
 template <> struct ModeTraits<2> { typedef double T; typedef v4d acc_t; };
 
+// Pad rows per q block of the LDS tile (see the bank layout note in mfma_tile).
+template <int H, int TB>
+__host__ __device__ inline int pad_rows(int NK) {
+  return (TB == 16 && ((NK - H) % 2) == 0) ? 1 : 0;
+}
+
 // One cell tile: stage f, then process every (l1, q1-group) work unit.
 template <int H, int SLOTS, int RT, int MODE>
 __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, unsigned char* lds_raw,
@@ -62,12 +69,28 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
   T* Qo = static_cast<T*>(p.Q);
   const int NK = p.NK;
   const int64_t cell0 = tile * TB;
-  // stage the coefficient tile: fs[n * TB + cell]
+  // Bank layout.  With 16-cell tiles an LDS row holds 16 consecutive banks, so
+  // rows of equal parity share banks; the two lane groups of a half-wave read
+  // rows NK-H apart.  When that distance is even, one zero pad row is inserted
+  // per q block between k = H-1 and k = H (the upper group then starts at
+  // NK-H+1, odd distance; for odd NK its first, duplicated row reads the pad,
+  // whose R weight is zero).
+  const int pd = pad_rows<H, TB>(NK);
+  const int NKp = NK + pd;
+  const int rows = p.NQ * NKp;
+  // stage the coefficient tile: fs[(q * NKp + k + pd*(k >= H)) * TB + cell]
   for (int idx = threadIdx.x; idx < TB * p.N; idx += blockDim.x) {
     const int cl = idx / p.N, n = idx - cl * p.N;
+    const int q = n / NK, k = n - q * NK;
     const int64_t cell = cell0 + cl;
-    fs[n * TB + cl] = (cell < p.B) ? f[cell * p.ldf + n] : T(0);
+    fs[(q * NKp + k + (k >= H ? pd : 0)) * TB + cl] = (cell < p.B) ? f[cell * p.ldf + n] : T(0);
   }
+  if (pd)
+    for (int idx = threadIdx.x; idx < TB * p.NQ; idx += blockDim.x) {
+      const int q = idx / TB, cl = idx - q * TB;
+      fs[(q * NKp + H) * TB + cl] = T(0);
+    }
+  (void)rows;
   if (threadIdx.x == 0) unit_ctr = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -78,7 +101,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
   // starts at 0, the upper at NK-H (for odd NK the middle row is in both halves;
   // the R tile holds zero for the copy in the upper half), so every gather is a
   // per-lane base plus a compile-time offset.
-  const int k2s = h2 ? NK - H : 0, k3s = h3 ? NK - H : 0;
+  const int k2s = h2 ? NK - H + pd : 0, k3s = h3 ? NK - H + pd : 0;
   const T* lane_u = fs + k2s * TB + cellj;
   const T* lane_w = fs + k3s * TB + cellj;
   // read-only routing rows: through the constant address space so that
@@ -86,7 +109,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
   typedef const __attribute__((address_space(4))) uint32_t cu32;
   typedef const __attribute__((address_space(4))) float cf32;
   typedef const __attribute__((address_space(4))) double cf64;
-  cu32* mq = (cu32*)p.mq;
+  cu32* mq = (cu32*)(pd ? p.mq_pad : p.mq);
   cf32* mg = (cf32*)p.mg;
   cf64* mg64 = (cf64*)p.mg64;
   while (true) {
@@ -118,22 +141,36 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
           e0 = __builtin_amdgcn_readfirstlane(e0);
           e1 = __builtin_amdgcn_readfirstlane(e1);
           if (e0 < e1) {
+            // software pipeline: the gathers of row e+1 are in flight while the
+            // outer product of row e accumulates (the arrays carry tail slack,
+            // whose row offsets point at LDS row 0)
             uint32_t qq = mq[e0];
             T gg = MODE == 2 ? (T)mg64[e0] : (T)mg[e0];
+            T fu[H], fw[H];
+            {
+              const T* pu = lane_u + (int)(qq & 0xffffu) * TB;     // q * NKp rows
+              const T* pw = lane_w + (int)(qq >> 16) * TB;
+#pragma unroll
+              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fw[a] = pw[a * TB]; }
+            }
             for (int e = e0; e < e1; ++e) {
-              // prefetch the next row (the arrays carry tail slack)
               const uint32_t qn = mq[e + 1];
               const T gn = MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1];
-              const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
-              const T* pw = lane_w + (int)(qq >> 16) * TB;
-              T uu[H], ww[H];
+              const T* pu = lane_u + (int)(qn & 0xffffu) * TB;
+              const T* pw = lane_w + (int)(qn >> 16) * TB;
+              T nu[H], nw[H];
 #pragma unroll
-              for (int a = 0; a < H; ++a) { uu[a] = gg * pu[a * TB]; ww[a] = pw[a * TB]; }
+              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; nw[a] = pw[a * TB]; }
+              T uu[H];
+#pragma unroll
+              for (int a = 0; a < H; ++a) uu[a] = gg * fu[a];
 #pragma unroll
               for (int a = 0; a < H; ++a)
 #pragma unroll
-                for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
-              qq = qn; gg = gn;
+                for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], fw[b], phi[a * H + b]);
+#pragma unroll
+              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fw[a] = nw[a]; }
+              gg = gn;
             }
           }
         } else {

@@ -148,6 +148,18 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   for (int pad = 0; pad < 8; ++pad) { mq.push_back(0u); mg.push_back(0.0f); mg64.push_back(0.0); }  // tail slack
   h->NGm = ngm;
   h->NSm = nsm;
+  // row offsets for 16-cell tiles with a pad row per q block (pitch NK+1)
+  std::vector<uint32_t> mq_pad;
+  {
+    const int Hh = (NK + 1) / 2;
+    if (tile_pad_rows(NK, Hh, 16)) {
+      mq_pad.resize(mq.size());
+      for (size_t i = 0; i < mq.size(); ++i) {
+        uint32_t q2 = (mq[i] & 0xffffu) / NK, q3 = (mq[i] >> 16) / NK;
+        mq_pad[i] = (q2 * (NK + 1)) | ((q3 * (NK + 1)) << 16);
+      }
+    }
+  }
   // MFMA geometry
   h->H = (NK + 1) / 2;
   h->RT = NK > 16 ? 2 : 1;
@@ -157,9 +169,10 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   const size_t limit = (size_t)std::min(dev_lds, 163840) - 512;
   h->lds_limit = (int)limit;
   // output states sharing the 16 MFMA columns, so that a tile of 16/SLOTS cells fits in LDS
+  h->H = (NK + 1) / 2;
   auto pick_slots = [&](size_t elem) {
     for (int sl : {1, 2, 4})
-      if ((size_t)h->N * (16 / sl) * elem <= limit) return sl;
+      if (tile_lds_bytes(h, sl, elem) <= limit) return sl;
     return 0;
   };
   h->SLOTS = pick_slots(4);
@@ -251,6 +264,8 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
       !upload(h, h->d_slice_off, slice_off, s) || !upload(h, h->d_sptr, sptr, s) ||
       !upload(h, h->d_mq, mq, s) || !upload(h, h->d_mg, mg, s))
     return false;
+  if (mq_pad.empty()) h->d_mq_pad = h->d_mq;
+  else if (!upload(h, h->d_mq_pad, mq_pad, s)) return false;
   h->d_check = dev_alloc<double>(h, h->check_blocks);
   if (!h->d_check) { set_error("device allocation failed"); return false; }
   return hipStreamSynchronize(s) == hipSuccess;
@@ -410,7 +425,7 @@ wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32
   if (slots != 1 && slots != 2 && slots != 4) return fail(WEFQ_EINVAL, "slots must be 1, 2 or 4");
   if (block != 256 && block != 512) return fail(WEFQ_EINVAL, "block must be 256 or 512");
   const size_t elem = precision == WEFQ_FP64 ? 8 : 4;
-  if ((size_t)h->N * (16 / slots) * elem > (size_t)h->lds_limit)
+  if (tile_lds_bytes(h, slots, elem) > (size_t)h->lds_limit)
     return fail(WEFQ_EUNSUPPORTED, "tile of 16/slots cells does not fit in LDS");
   if (precision == WEFQ_FP64) h->SLOTS64 = slots; else h->SLOTS = slots;
   h->block = block;

@@ -34,6 +34,7 @@ struct wefq_core {
   int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
   uint32_t* d_mq = nullptr;            // merged entries: q2*NK | (q3*NK) << 16
+  uint32_t* d_mq_pad = nullptr;        // the same with the padded pitch NK+1 (16-cell tiles)
   float* d_mg = nullptr;               // merged weights
   double* d_mg64 = nullptr;            // merged weights, FP64
   float* d_Rt32 = nullptr;             // [NTm][H*H][64]  (rows k1 < 16)
@@ -57,6 +58,16 @@ struct wefq_core {
 };
 
 namespace wefq {
+
+// Pad rows per q block of a 16-cell LDS tile (must match pad_rows in apply_tile.h).
+inline int tile_pad_rows(int NK, int H, int TB) { return (TB == 16 && ((NK - H) % 2) == 0) ? 1 : 0; }
+
+// LDS bytes of one coefficient tile of 16/slots cells.
+inline size_t tile_lds_bytes(const wefq_core* h, int slots, size_t elem) {
+  const int TB = 16 / slots;
+  const int pd = tile_pad_rows(h->NK, h->H, TB);
+  return (size_t)h->NQ * (h->NK + pd) * TB * elem;
+}
 
 // Error reporting helper (thread-local message).
 void set_error(const std::string& msg);
