@@ -235,7 +235,7 @@ def bench_uneven(args, torch, wefq, synth):
     total = cfg["cells"]
     size = rng.choice(np.array(cfg["sizes"]), size=total)
     model = rng.choice(np.array(["hs", "vhs"]), size=total)
-    segs, flop = [], 0.0
+    segs, lds_max, flop = [], [], 0.0
     for K in cfg["sizes"]:
         for m in ("hs", "vhs"):
             B = int(np.sum((size == K) & (model == m)))
@@ -243,19 +243,27 @@ def bench_uneven(args, torch, wefq, synth):
                 continue
             log(f"[uneven] core {m} K=L={K}, {B} cells")
             core = wefq.Core(m, K, K, gamma=1.0 if m == "hs" else 0.5, device=0, precisions=("fp32",))
+            s_lds = core.tune_get("fp32")[0]  # the library default, read before tuning
             s, blk, _ = autotune.tune(core, "fp32", cells=min(B, 4096), reps=2)
             f = torch.tensor(synth.perturbed_maxwellian(K, K, B, seed=cfg["seed"] + 10 * K + (m == "hs")),
                              dtype=torch.float32, device=dev)
             segs.append((core, f, torch.empty_like(f), s))
+            lds_max.append(s_lds)
             flop += core.info["flop_alg_per_cell"] * B
+    # plan-level choice: per-core autotuned shapes (tuned on each segment alone), or the
+    # library's default shapes (largest tiles that fit LDS: fewer coefficient-tile reloads
+    # per cell, which pays once the whole mix fills the chip), each at 256 or 512 threads
+    default = [(c, f, q, s) for (c, f, q, _), s in zip(segs, lds_max)]
     best = None
-    for blk in (256, 512):
-        plan = wefq.Plan(segs, precision="fp32", block=blk)
-        plan.launch()
-        ms, _ = time_steps(lambda: plan.launch(), 3, stream, torch)
-        if best is None or np.mean(ms) < best[1]:
-            best = (plan, float(np.mean(ms)), blk)
-    plan, _, blk = best
+    for name, cand in (("autotuned", segs), ("default", default)):
+        for blk in (256, 512):
+            plan = wefq.Plan(cand, precision="fp32", block=blk)
+            plan.launch()
+            ms, _ = time_steps(lambda: plan.launch(), 3, stream, torch)
+            log(f"[uneven] plan {name} block {blk}: {np.mean(ms):.2f} ms")
+            if best is None or np.mean(ms) < best[1]:
+                best = (plan, float(np.mean(ms)), blk, name, cand)
+    plan, _, blk, shape_name, segs_used = best
     for _ in range(args.warmup):
         plan.launch()
     ms, wall = time_steps(lambda: plan.launch(), args.steps, stream, torch)
@@ -272,7 +280,8 @@ def bench_uneven(args, torch, wefq, synth):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": "uneven_20000_K4-16_hs_vhs", "cells": total,
                       "segments": [{"model": c.model, "K": c.K, "cells": f.shape[0], "slots": s}
-                                   for c, f, _, s in segs], "block": blk, "plan": plan.info},
+                                   for c, f, _, s in segs_used],
+                      "tile_shapes": shape_name, "block": blk, "plan": plan.info},
            "p50_ms": float(np.percentile(ms, 50)), "p99_ms": float(np.percentile(ms, 99)),
            "roofline": {"bound": "mfma", "achieved": flop / t / 1e12, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                         "frac": flop / t / 1e12 / PEAK["fp32"], "traffic": None},

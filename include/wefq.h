@@ -120,8 +120,10 @@ const char* wefq_last_error(void);
 /* Tile shape used by wefq_apply_Q for one precision of a core: slots = output
  * states sharing the 16 MFMA columns (1, 2 or 4; the cell tile is 16/slots cells
  * and must fit in LDS), block = threads per workgroup (256 or 512).  Results are
- * bitwise independent of the shape.  Chosen by the autotuner; not thread-safe
- * with concurrent applies of the same core. */
+ * bitwise independent of the shape.  The default, set by wefq_build_core, is the
+ * largest tile that fits in LDS with a kernel that spills at most 128 bytes of
+ * registers per lane, at 512 threads; the autotuner may replace it.  Each precision keeps its own shape.
+ * Not thread-safe with concurrent applies of the same core. */
 wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32_t block);
 wefq_status wefq_tune_get(wefq_handle h, int32_t precision, int32_t* slots, int32_t* block);
 

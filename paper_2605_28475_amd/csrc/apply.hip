@@ -114,6 +114,60 @@ static hipError_t launch_mfma_t(const MfmaParams& p, int64_t ntiles, int block, 
   return hipGetLastError();
 }
 
+template <int H, int SLOTS, int RT, int MODE>
+static int spill_t() {
+  hipFuncAttributes a;
+  if (hipFuncGetAttributes(&a, (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE>) != hipSuccess) return -1;
+  return (int)a.localSizeBytes;
+}
+
+// One instance per (H, slots, RT, mode), chosen at run time; every dispatcher below
+// goes through this switch so that the launch and the spill query see the same kernels.
+template <int H, int RT, int MODE>
+static int spill_s(int slots) {
+  switch (slots) {
+    case 1: return spill_t<H, 1, RT, MODE>();
+    case 2: return spill_t<H, 2, RT, MODE>();
+    case 4: return spill_t<H, 4, RT, MODE>();
+    default: return -1;
+  }
+}
+
+template <int H>
+static int spill_h(int mode, int slots, int rt) {
+  if (rt == 2) {
+    if constexpr (H >= 8) {
+      switch (mode) {
+        case 0: return spill_s<H, 2, 0>(slots);
+        case 1: return spill_s<H, 2, 1>(slots);
+        case 2: return spill_s<H, 2, 2>(slots);
+      }
+    }
+    return -1;
+  }
+  switch (mode) {
+    case 0: return spill_s<H, 1, 0>(slots);
+    case 1: return spill_s<H, 1, 1>(slots);
+    case 2: return spill_s<H, 1, 2>(slots);
+  }
+  return -1;
+}
+
+int mfma_spill_bytes(const wefq_core* h, int mode, int slots) {
+  switch (h->H) {
+    case 1: return spill_h<1>(mode, slots, h->RT);
+    case 2: return spill_h<2>(mode, slots, h->RT);
+    case 3: return spill_h<3>(mode, slots, h->RT);
+    case 4: return spill_h<4>(mode, slots, h->RT);
+    case 5: return spill_h<5>(mode, slots, h->RT);
+    case 6: return spill_h<6>(mode, slots, h->RT);
+    case 7: return spill_h<7>(mode, slots, h->RT);
+    case 8: return spill_h<8>(mode, slots, h->RT);
+    case 9: return spill_h<9>(mode, slots, h->RT);
+    default: return -1;
+  }
+}
+
 template <int H, int RT, int MODE>
 static hipError_t launch_mfma_s(const MfmaParams& p, int slots, int64_t ntiles, int block, size_t lds,
                                 hipStream_t s) {
@@ -153,26 +207,27 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   p.f = f; p.Q = Q; p.B = B; p.ldf = ldf; p.ldq = ldq;
   p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
   p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
-  p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
+  p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.spair = h->d_spair; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
   p.mg = h->d_mg; p.mg64 = h->d_mg64;
   p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
   p.R16_32 = h->d_R16_32; p.R16_64 = h->d_R16_64;
-  const int mode = precision == WEFQ_FP64 ? 2 : (precision == WEFQ_BF16X3 ? 1 : 0);
-  const int slots = mode == 2 ? h->SLOTS64 : h->SLOTS;
+  const int mode = mfma_mode(precision);
+  if (mode < 0) return hipErrorInvalidValue;
+  const int slots = h->slots[mode], block = h->block[mode];
   if (slots == 0) return hipErrorInvalidValue;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   switch (h->H) {
-    case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 2: return launch_mfma_h<2>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 3: return launch_mfma_h<3>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 4: return launch_mfma_h<4>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 5: return launch_mfma_h<5>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 6: return launch_mfma_h<6>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 7: return launch_mfma_h<7>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 8: return launch_mfma_h<8>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
-    case 9: return launch_mfma_h<9>(p, mode, slots, h->RT, ntiles, h->block, lds, s);
+    case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 2: return launch_mfma_h<2>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 3: return launch_mfma_h<3>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 4: return launch_mfma_h<4>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 5: return launch_mfma_h<5>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 6: return launch_mfma_h<6>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 7: return launch_mfma_h<7>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 8: return launch_mfma_h<8>(p, mode, slots, h->RT, ntiles, block, lds, s);
+    case 9: return launch_mfma_h<9>(p, mode, slots, h->RT, ntiles, block, lds, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -24,6 +24,7 @@ struct MfmaParams {
   const int* chan_begin;   // [L+2]
   const int* slice_off;    // [NTm]
   const int* sptr;         // slices + 1
+  const int* spair;        // per slice: first single row; rows [sptr[s], spair[s]) are q2 pairs
   const uint32_t* mq;      // q2*NKp | (q3*NKp) << 16: LDS row offsets of the two gathered states
   const uint32_t* mq_pad;  // the same with the padded row pitch (16-cell tiles with a pad row)
   const float* mg;         // merged weights (FP32 / BF16X3)
@@ -137,15 +138,56 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
         T phi[U * 8];
 #pragma unroll
         for (int t = 0; t < U * 8; ++t) phi[t] = T(0);
+        // The slice's rows come as pairs sharing q2, then single rows.  A pair adds
+        // f_{k2,q2} (g_a f_{k3,q3a} + g_b f_{k3,q3b}) to Phi: one outer product for
+        // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.
+        int ep = p.spair[s];
+        if (!qvalid) ep = e0;
         if (SLOTS == 1) {               // the slice is shared by the whole wave
           e0 = __builtin_amdgcn_readfirstlane(e0);
           e1 = __builtin_amdgcn_readfirstlane(e1);
-          if (e0 < e1) {
-            // software pipeline: the gathers of row e+1 are in flight while the
-            // outer product of row e accumulates (the arrays carry tail slack,
-            // whose row offsets point at LDS row 0)
-            uint32_t qq = mq[e0];
-            T gg = MODE == 2 ? (T)mg64[e0] : (T)mg[e0];
+          ep = __builtin_amdgcn_readfirstlane(ep);
+          // software pipeline: the gathers of the next row (pair) are in flight
+          // while the outer product of the current one accumulates (the arrays
+          // carry tail slack, whose row offsets point at LDS row 0)
+          if (e0 < ep) {
+            uint32_t qa = mq[e0], qb = mq[e0 + 1];
+            T ga = MODE == 2 ? (T)mg64[e0] : (T)mg[e0];
+            T gb = MODE == 2 ? (T)mg64[e0 + 1] : (T)mg[e0 + 1];
+            T fu[H], fa[H], fb[H];
+            {
+              const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
+              const T* pa = lane_w + (int)(qa >> 16) * TB;
+              const T* pb = lane_w + (int)(qb >> 16) * TB;
+#pragma unroll
+              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fa[a] = pa[a * TB]; fb[a] = pb[a * TB]; }
+            }
+            for (int e = e0; e < ep; e += 2) {
+              const uint32_t qna = mq[e + 2], qnb = mq[e + 3];
+              const T gna = MODE == 2 ? (T)mg64[e + 2] : (T)mg[e + 2];
+              const T gnb = MODE == 2 ? (T)mg64[e + 3] : (T)mg[e + 3];
+              const T* pu = lane_u + (int)(qna & 0xffffu) * TB;
+              const T* pa = lane_w + (int)(qna >> 16) * TB;
+              const T* pb = lane_w + (int)(qnb >> 16) * TB;
+              T nu[H], na[H], nb[H];
+#pragma unroll
+              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; na[a] = pa[a * TB]; nb[a] = pb[a * TB]; }
+              T ww[H];
+#pragma unroll
+              for (int b = 0; b < H; ++b) ww[b] = fma(gb, fb[b], ga * fa[b]);
+#pragma unroll
+              for (int a = 0; a < H; ++a)
+#pragma unroll
+                for (int b = 0; b < H; ++b) phi[a * H + b] = fma(fu[a], ww[b], phi[a * H + b]);
+#pragma unroll
+              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fa[a] = na[a]; fb[a] = nb[a]; }
+              ga = gna;
+              gb = gnb;
+            }
+          }
+          if (ep < e1) {
+            uint32_t qq = mq[ep];
+            T gg = MODE == 2 ? (T)mg64[ep] : (T)mg[ep];
             T fu[H], fw[H];
             {
               const T* pu = lane_u + (int)(qq & 0xffffu) * TB;     // q * NKp rows
@@ -153,7 +195,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
 #pragma unroll
               for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fw[a] = pw[a * TB]; }
             }
-            for (int e = e0; e < e1; ++e) {
+            for (int e = ep; e < e1; ++e) {
               const uint32_t qn = mq[e + 1];
               const T gn = MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1];
               const T* pu = lane_u + (int)(qn & 0xffffu) * TB;
@@ -174,16 +216,36 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
             }
           }
         } else {
-          const int len = e1 - e0;
-          int maxlen = len;
+          // lanes of different output states walk different slices: iterate to the
+          // longest pair and single runs of the wave, masking the shorter ones
+          const int np = (ep - e0) >> 1, ns = e1 - ep;
+          int maxp = np, maxs = ns;
 #pragma unroll
           for (int off = TB; off < 16; off <<= 1) {
-            const int o = __shfl_xor(maxlen, off);
-            maxlen = maxlen > o ? maxlen : o;
+            const int op = __shfl_xor(maxp, off), os = __shfl_xor(maxs, off);
+            maxp = maxp > op ? maxp : op;
+            maxs = maxs > os ? maxs : os;
           }
-          for (int i = 0; i < maxlen; ++i) {
-            const bool in = i < len;
-            const int e = in ? e0 + i : e0;
+          for (int i = 0; i < maxp; ++i) {
+            const bool in = i < np;
+            const int e = in ? e0 + 2 * i : e0;
+            const uint32_t qa = in ? mq[e] : 0u, qb = in ? mq[e + 1] : 0u;
+            const T ga = in ? (MODE == 2 ? (T)mg64[e] : (T)mg[e]) : T(0);
+            const T gb = in ? (MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1]) : T(0);
+            const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
+            const T* pa = lane_w + (int)(qa >> 16) * TB;
+            const T* pb = lane_w + (int)(qb >> 16) * TB;
+            T fu[H], ww[H];
+#pragma unroll
+            for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; ww[a] = fma(gb, pb[a * TB], ga * pa[a * TB]); }
+#pragma unroll
+            for (int a = 0; a < H; ++a)
+#pragma unroll
+              for (int b = 0; b < H; ++b) phi[a * H + b] = fma(fu[a], ww[b], phi[a * H + b]);
+          }
+          for (int i = 0; i < maxs; ++i) {
+            const bool in = i < ns;
+            const int e = in ? ep + i : e0;
             const uint32_t qq = in ? mq[e] : 0u;
             const T gg = in ? (MODE == 2 ? (T)mg64[e] : (T)mg[e]) : T(0);
             const T* pu = lane_u + (int)(qq & 0xffffu) * TB;

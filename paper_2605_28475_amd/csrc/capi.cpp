@@ -131,17 +131,33 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
         {(uint32_t)(r.q2 * NK) | ((uint32_t)(r.q3 * NK) << 16), g});
     ++ngm;
   }
-  std::vector<int> sptr(slices.size() + 1, 0);
+  // Within a slice, rows that share q2 are stored as consecutive pairs first (the
+  // kernel folds a pair into one outer product: f_{.,q2} x (g_a f_{.,q3a} + g_b f_{.,q3b})),
+  // then the remaining single rows; spair[s] is the first single row of slice s.
+  std::vector<int> sptr(slices.size() + 1, 0), spair(slices.size(), 0);
   std::vector<uint32_t> mq;
   std::vector<float> mg;
   std::vector<double> mg64;
   int nsm = 0;
+  typedef std::pair<uint32_t, double> Ent;
   for (size_t i = 0; i < slices.size(); ++i) {
     auto& sl = slices[i];
-    std::sort(sl.begin(), sl.end(), [](const std::pair<uint32_t, double>& a, const std::pair<uint32_t, double>& b) {
+    std::sort(sl.begin(), sl.end(), [](const Ent& a, const Ent& b) {
+      return (a.first & 0xffff) != (b.first & 0xffff) ? (a.first & 0xffff) < (b.first & 0xffff) : (a.first >> 16) < (b.first >> 16);
+    });
+    std::vector<Ent> singles;
+    for (size_t a = 0; a < sl.size();) {
+      size_t b = a;
+      while (b < sl.size() && (sl[b].first & 0xffff) == (sl[a].first & 0xffff)) ++b;
+      for (; a + 1 < b; a += 2)
+        for (size_t t = a; t < a + 2; ++t) { mq.push_back(sl[t].first); mg.push_back((float)sl[t].second); mg64.push_back(sl[t].second); }
+      if (a < b) singles.push_back(sl[a++]);
+    }
+    spair[i] = (int)mq.size();
+    std::sort(singles.begin(), singles.end(), [](const Ent& a, const Ent& b) {
       return (a.first >> 16) != (b.first >> 16) ? (a.first >> 16) < (b.first >> 16) : (a.first & 0xffff) < (b.first & 0xffff);
     });
-    for (auto& e : sl) { mq.push_back(e.first); mg.push_back((float)e.second); mg64.push_back(e.second); }
+    for (auto& e : singles) { mq.push_back(e.first); mg.push_back((float)e.second); mg64.push_back(e.second); }
     sptr[i + 1] = (int)mq.size();
     if (!sl.empty()) ++nsm;
   }
@@ -168,16 +184,28 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     dev_lds = 65536;
   const size_t limit = (size_t)std::min(dev_lds, 163840) - 512;
   h->lds_limit = (int)limit;
-  // output states sharing the 16 MFMA columns, so that a tile of 16/SLOTS cells fits in LDS
-  h->H = (NK + 1) / 2;
-  auto pick_slots = [&](size_t elem) {
-    for (int sl : {1, 2, 4})
-      if (tile_lds_bytes(h, sl, elem) <= limit) return sl;
-    return 0;
+  // Default tile shape per mode: the fewest output states sharing the 16 MFMA
+  // columns (largest cell tile, fewest coefficient-tile reloads per cell) whose
+  // LDS tile fits and whose kernel instance spills at most a few registers; when
+  // every fitting instance spills more, the largest fitting tile.  (Measured at
+  // K = L = 12 and 16: a 44-byte spill costs less than doubling the tile reloads,
+  // a 268-byte spill costs more.)
+  constexpr int kMaxSpillBytes = 128;
+  auto pick_slots = [&](int mode) {
+    const size_t elem = mode == 2 ? 8 : 4;
+    int first_fit = 0;
+    for (int sl : {1, 2, 4}) {
+      if (tile_lds_bytes(h, sl, elem) > limit) continue;
+      if (!first_fit) first_fit = sl;
+      const int spill = mfma_spill_bytes(h, mode, sl);
+      if (spill >= 0 && spill <= kMaxSpillBytes) return sl;
+    }
+    return first_fit;
   };
-  h->SLOTS = pick_slots(4);
-  h->SLOTS64 = pick_slots(8);
-  h->TB = h->SLOTS ? 16 / h->SLOTS : 0;
+  for (int mode = 0; mode < 3; ++mode) {
+    h->slots[mode] = pick_slots(mode);
+    h->block[mode] = 512;
+  }
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;   // RT == 2: NK = 17
   // A-operand value for lane group r at step t: the group's quadrant starts at
   // 0 (lower half) or NK-H (upper half); a row or column that the upper half
@@ -192,7 +220,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     return Rm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3];
   };
   bool want32 = h->precisions & WEFQ_FP32, want16 = h->precisions & WEFQ_BF16X3, want64 = h->precisions & WEFQ_FP64;
-  if (((want32 || want16) && h->SLOTS == 0) || (want64 && h->SLOTS64 == 0)) {
+  if ((want32 && h->slots[0] == 0) || (want16 && h->slots[1] == 0) || (want64 && h->slots[2] == 0)) {
     set_error("coefficient tile does not fit in LDS for this truncation");
     return false;
   }
@@ -250,7 +278,8 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
       for (int m = chan_begin[l1]; m < chan_begin[l1 + 1]; ++m)
         for (int q = qb; q < qb + nq; ++q) {
           int si = slice_off[m] + q - l1 * l1;
-          cost += (double)(sptr[si + 1] - sptr[si]) * (HH + 2 * H) + HH * RT * 8.0;
+          const int npair = (spair[si] - sptr[si]) / 2, nsingle = sptr[si + 1] - spair[si];
+          cost += (double)npair * (HH + 5 * H) + (double)nsingle * (HH + 3 * H) + HH * RT * 8.0;
         }
       units.push_back({l1, qb, nq, cost});
     }
@@ -262,6 +291,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   h->nunits = (int)units.size();
   if (!upload(h, h->d_units, uarr, s) || !upload(h, h->d_chan_begin, chan_begin, s) ||
       !upload(h, h->d_slice_off, slice_off, s) || !upload(h, h->d_sptr, sptr, s) ||
+      !upload(h, h->d_spair, spair, s) ||
       !upload(h, h->d_mq, mq, s) || !upload(h, h->d_mg, mg, s))
     return false;
   if (mq_pad.empty()) h->d_mq_pad = h->d_mq;
@@ -420,22 +450,24 @@ wefq_status wefq_check_conservation(wefq_handle h, int32_t precision, const void
 
 wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32_t block) {
   if (!h) return fail(WEFQ_EINVAL, "null handle");
-  if (precision != WEFQ_FP64 && precision != WEFQ_FP32 && precision != WEFQ_BF16X3)
-    return fail(WEFQ_EINVAL, "tile shapes exist for FP64, FP32 and BF16X3");
+  const int mode = mfma_mode(precision);
+  if (mode < 0) return fail(WEFQ_EINVAL, "tile shapes exist for FP64, FP32 and BF16X3");
   if (slots != 1 && slots != 2 && slots != 4) return fail(WEFQ_EINVAL, "slots must be 1, 2 or 4");
   if (block != 256 && block != 512) return fail(WEFQ_EINVAL, "block must be 256 or 512");
-  const size_t elem = precision == WEFQ_FP64 ? 8 : 4;
+  const size_t elem = mode == 2 ? 8 : 4;
   if (tile_lds_bytes(h, slots, elem) > (size_t)h->lds_limit)
     return fail(WEFQ_EUNSUPPORTED, "tile of 16/slots cells does not fit in LDS");
-  if (precision == WEFQ_FP64) h->SLOTS64 = slots; else h->SLOTS = slots;
-  h->block = block;
+  h->slots[mode] = slots;
+  h->block[mode] = block;
   return WEFQ_OK;
 }
 
 wefq_status wefq_tune_get(wefq_handle h, int32_t precision, int32_t* slots, int32_t* block) {
   if (!h || !slots || !block) return fail(WEFQ_EINVAL, "null argument");
-  *slots = precision == WEFQ_FP64 ? h->SLOTS64 : h->SLOTS;
-  *block = h->block;
+  const int mode = mfma_mode(precision);
+  if (mode < 0) return fail(WEFQ_EINVAL, "tile shapes exist for FP64, FP32 and BF16X3");
+  *slots = h->slots[mode];
+  *block = h->block[mode];
   return WEFQ_OK;
 }
 

@@ -145,7 +145,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     if (g.B > 0 && (!g.f || !g.Q)) return plan_fail(WEFQ_EINVAL, "null segment buffer");
     if (g.ld_f < h->N || g.ld_q < h->N) return plan_fail(WEFQ_EINVAL, "leading dimension smaller than N");
     if (((uintptr_t)g.f | (uintptr_t)g.Q) & (elem - 1)) return plan_fail(WEFQ_EINVAL, "buffers must be aligned to the element size");
-    int slots = g.slots ? g.slots : (mode == 2 ? h->SLOTS64 : h->SLOTS);
+    int slots = g.slots ? g.slots : h->slots[mode];
     if (slots != 1 && slots != 2 && slots != 4) return plan_fail(WEFQ_EINVAL, "slots must be 0, 1, 2 or 4");
     const int TB = 16 / slots;
     const size_t need = tile_lds_bytes(h, slots, elem);
@@ -157,7 +157,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     p.f = g.f; p.Q = g.Q; p.B = g.B; p.ldf = g.ld_f; p.ldq = g.ld_q;
     p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
     p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
-    p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
+    p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.spair = h->d_spair; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
     p.mg = h->d_mg; p.mg64 = h->d_mg64;
     p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
     p.R16_32 = h->d_R16_32; p.R16_64 = h->d_R16_64;

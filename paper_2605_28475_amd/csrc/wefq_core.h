@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/wefq.h"
 #include "wefq_host.h"
 
 struct wefq_core {
@@ -28,11 +29,13 @@ struct wefq_core {
   double* d_ent_g = nullptr;
 
   // MFMA path (merged channels sorted by l1)
-  int H = 0, RT = 0, TB = 0, SLOTS = 0, SLOTS64 = 0;   // MFMA geometry (SLOTS: FP32 tiles, SLOTS64: FP64)
-                                       // RT == 2 marks NK = 17 (row 16 on the VALU)
+  int H = 0, RT = 0;                   // quadrant size; RT == 2 marks NK = 17 (row 16 on the VALU)
+  int slots[3] = {0, 0, 0};            // tile shape per mode (0 FP32, 1 BF16X3, 2 FP64): the cell
+  int block[3] = {512, 512, 512};      // tile is 16/slots cells; block = threads per workgroup
   int* d_chan_begin = nullptr;         // L + 2: merged channels of l1 are [begin[l1], begin[l1+1])
   int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
+  int* d_spair = nullptr;              // per slice: first single row (rows before it come in q2 pairs)
   uint32_t* d_mq = nullptr;            // merged entries: q2*NK | (q3*NK) << 16
   uint32_t* d_mq_pad = nullptr;        // the same with the padded pitch NK+1 (16-cell tiles)
   float* d_mg = nullptr;               // merged weights
@@ -48,7 +51,6 @@ struct wefq_core {
   int GQ = 0;                          // q1 per unit
   double tile_cost = 0.0;              // estimated cost of one full 16-cell tile (scheduling only)
   int lds_limit = 0;                   // usable LDS bytes per workgroup
-  int block = 512;                     // threads per workgroup of the MFMA kernel
 
   // conservation check scratch
   double* d_check = nullptr;
@@ -61,6 +63,11 @@ namespace wefq {
 
 // Pad rows per q block of a 16-cell LDS tile (must match pad_rows in apply_tile.h).
 inline int tile_pad_rows(int NK, int H, int TB) { return (TB == 16 && ((NK - H) % 2) == 0) ? 1 : 0; }
+
+// Kernel mode of a precision: 0 FP32, 1 BF16X3, 2 FP64 (tiled); -1 otherwise.
+inline int mfma_mode(int precision) {
+  return precision == WEFQ_FP32 ? 0 : precision == WEFQ_BF16X3 ? 1 : precision == WEFQ_FP64 ? 2 : -1;
+}
 
 // LDS bytes of one coefficient tile of 16/slots cells.
 inline size_t tile_lds_bytes(const wefq_core* h, int slots, size_t elem) {
@@ -95,6 +102,9 @@ hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int
                              int64_t ldf, int64_t ldq, hipStream_t s);
 hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, void* Q,
                              int64_t B, int64_t ldf, int64_t ldq, hipStream_t s);
+// Private (scratch) bytes per lane of the MFMA kernel instance of a tile shape:
+// nonzero when it spills registers.  Returns -1 for a shape with no instance.
+int mfma_spill_bytes(const wefq_core* h, int mode, int slots);
 hipError_t launch_check(const wefq_core* h, int precision, const void* Q, int64_t B,
                         int64_t ldq, hipStream_t s);
 
