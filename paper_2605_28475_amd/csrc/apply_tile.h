@@ -110,30 +110,61 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
   typedef const __attribute__((address_space(4))) uint32_t cu32;
   typedef const __attribute__((address_space(4))) float cf32;
   typedef const __attribute__((address_space(4))) double cf64;
+  // (the work-unit and slice tables too: their indices are wave-uniform, and scalar
+  // loads keep them off the vector-memory counter that the R-tile loads occupy)
+  typedef const __attribute__((address_space(4))) int ci32;
+  ci32* units = (ci32*)p.units;
+  ci32* chan_begin = (ci32*)p.chan_begin;
+  ci32* slice_off = (ci32*)p.slice_off;
+  ci32* sptr = (ci32*)p.sptr;
+  ci32* spair = (ci32*)p.spair;
   cu32* mq = (cu32*)(pd ? p.mq_pad : p.mq);
   cf32* mg = (cf32*)p.mg;
   cf64* mg64 = (cf64*)p.mg64;
   while (true) {
     int u = 0;
     if (lane == 0) u = atomicAdd(&unit_ctr, 1);
-    u = __shfl(u, 0);
+    u = __builtin_amdgcn_readfirstlane(__shfl(u, 0));
     if (u >= p.nunits) break;
-    const int l1 = p.units[3 * u], qb = p.units[3 * u + 1], nq = p.units[3 * u + 2];
+    const int l1 = units[3 * u], qb = units[3 * u + 1], nq = units[3 * u + 2];
     // RT == 2 marks NK = 17: rows 0..15 on MFMA, row 16 as a VALU dot product
     acc_t acc[NP][1];
     T acc16[NP];
 #pragma unroll
     for (int gi = 0; gi < NP; ++gi) { acc[gi][0] = (acc_t){0, 0, 0, 0}; acc16[gi] = T(0); }
-    const int cb = p.chan_begin[l1], ce = p.chan_begin[l1 + 1];
+    const int cb = chan_begin[l1], ce = chan_begin[l1 + 1];
     for (int ct = cb; ct < ce; ++ct) {
-      const int soff = p.slice_off[ct] - l1 * l1;
+      const int soff = slice_off[ct] - l1 * l1;
+      // The channel's R tile is the MFMA A operand for every q1 of the unit.  When
+      // registers allow, it is loaded once per channel ahead of the first coupling,
+      // so its latency hides behind the VALU work; otherwise it streams in batches.
+      constexpr bool HOIST = MODE == 2 ? (H <= 4) : (H <= 7);
+      float a32[HOIST && MODE == 0 ? HH : 1];
+      double a64[HOIST && MODE == 2 ? HH : 1];
+      v8bf ahi[HOIST && MODE == 1 ? U : 1], alo[HOIST && MODE == 1 ? U : 1];
+      if constexpr (HOIST && MODE == 0) {
+        const float* At = p.Rt32 + ((int64_t)ct * HH) * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < HH; ++t) a32[t] = At[t * 64];
+      } else if constexpr (HOIST && MODE == 2) {
+        const double* At = p.Rt64 + ((int64_t)ct * HH) * 64 + lane;
+#pragma unroll
+        for (int t = 0; t < HH; ++t) a64[t] = At[t * 64];
+      } else if constexpr (HOIST && MODE == 1) {
+#pragma unroll
+        for (int uu8 = 0; uu8 < U; ++uu8) {
+          const int64_t off = (((int64_t)ct * U + uu8) * 64 + lane) * 8;
+          ahi[uu8] = *reinterpret_cast<const v8bf*>(p.Rhi + off);
+          alo[uu8] = *reinterpret_cast<const v8bf*>(p.Rlo + off);
+        }
+      }
 #pragma unroll
       for (int gi = 0; gi < NP; ++gi) {
         if (gi * SLOTS >= nq) break;
         const int qi = gi * SLOTS + slot;
         const bool qvalid = qi < nq;
         const int s = soff + qb + (qvalid ? qi : 0);
-        int e0 = p.sptr[s], e1 = p.sptr[s + 1];
+        int e0 = sptr[s], e1 = sptr[s + 1];
         if (!qvalid) e1 = e0;
         T phi[U * 8];
 #pragma unroll
@@ -141,7 +172,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
         // The slice's rows come as pairs sharing q2, then single rows.  A pair adds
         // f_{k2,q2} (g_a f_{k3,q3a} + g_b f_{k3,q3b}) to Phi: one outer product for
         // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.
-        int ep = p.spair[s];
+        int ep = spair[s];
         if (!qvalid) ep = e0;
         if (SLOTS == 1) {               // the slice is shared by the whole wave
           e0 = __builtin_amdgcn_readfirstlane(e0);
@@ -259,7 +290,15 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
               for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
           }
         }
-        if constexpr (MODE == 0) {
+        if constexpr (HOIST && MODE == 0) {
+#pragma unroll
+          for (int t = 0; t < HH; ++t)
+            acc[gi][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[t], phi[t], acc[gi][0], 0, 0, 0);
+        } else if constexpr (HOIST && MODE == 2) {
+#pragma unroll
+          for (int t = 0; t < HH; ++t)
+            acc[gi][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[t], phi[t], acc[gi][0], 0, 0, 0);
+        } else if constexpr (MODE == 0) {
 #pragma unroll
           for (int rt = 0; rt < 1; ++rt) {
             const float* At = p.Rt32 + ((int64_t)ct * HH) * 64 + lane;
@@ -305,8 +344,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
 #pragma unroll
             for (int rt = 0; rt < 1; ++rt) {
               const int64_t off = (((int64_t)ct * U + uu8) * 64 + lane) * 8;
-              const v8bf ah = *reinterpret_cast<const v8bf*>(p.Rhi + off);
-              const v8bf al = *reinterpret_cast<const v8bf*>(p.Rlo + off);
+              const v8bf ah = HOIST ? ahi[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rhi + off);
+              const v8bf al = HOIST ? alo[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rlo + off);
               acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[gi][rt], 0, 0, 0);
               acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[gi][rt], 0, 0, 0);
               acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[gi][rt], 0, 0, 0);
