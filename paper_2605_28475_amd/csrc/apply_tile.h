@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "wefq_core.h"
+
 namespace wefq {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -20,7 +22,7 @@ struct MfmaParams {
   int64_t B, ldf, ldq;
   int NK, NQ, N;
   int nunits;
-  const int* units;        // [nunits][3]
+  const int* units;        // [nunits][UNIT_STRIDE]: l1, count, q1 values
   const int* chan_begin;   // [L+2]
   const int* slice_off;    // [NTm]
   const int* sptr;         // slices + 1
@@ -39,6 +41,7 @@ struct MfmaParams {
 
 // output states per work unit (fewer when NK > 16 needs two accumulator row tiles)
 __host__ __device__ constexpr int gq_for(int H) { return H >= 8 ? 4 : 8; }
+
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // MODE 0: FP32 MFMA, 1: split BF16x3 MFMA, 2: FP64 MFMA.
@@ -126,7 +129,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
     if (lane == 0) u = atomicAdd(&unit_ctr, 1);
     u = __builtin_amdgcn_readfirstlane(__shfl(u, 0));
     if (u >= p.nunits) break;
-    const int l1 = units[3 * u], qb = units[3 * u + 1], nq = units[3 * u + 2];
+    // unit record: l1, count, then the unit's q1 values; with several output states
+    // per MFMA column group, consecutive entries hold m1 and -m1, whose slices have
+    // similar lengths, so the masked coupling loops waste little
+    const int ub = UNIT_STRIDE * u;
+    const int l1 = units[ub], nq = units[ub + 1];
     // RT == 2 marks NK = 17: rows 0..15 on MFMA, row 16 as a VALU dot product
     acc_t acc[NP][1];
     T acc16[NP];
@@ -163,7 +170,11 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
         if (gi * SLOTS >= nq) break;
         const int qi = gi * SLOTS + slot;
         const bool qvalid = qi < nq;
-        const int s = soff + qb + (qvalid ? qi : 0);
+        int q1s = units[ub + 2 + gi * SLOTS];
+#pragma unroll
+        for (int sl = 1; sl < SLOTS; ++sl)
+          if (slot == sl && gi * SLOTS + sl < nq) q1s = units[ub + 2 + gi * SLOTS + sl];
+        const int s = soff + q1s;
         int e0 = sptr[s], e1 = sptr[s + 1];
         if (!qvalid) e1 = e0;
         T phi[U * 8];
@@ -290,6 +301,12 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
               for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
           }
         }
+        // Radial contraction of the slice on the matrix cores.  The wave raises its
+        // issue priority for the MFMA block, so the matrix core is refilled promptly
+        // while the other wave of the SIMD issues its coupling VALU work; the priority
+        // switches also keep the compiler from hoisting this block's operand
+        // preparation into the coupling loops (which spills registers at H = 9).
+        __builtin_amdgcn_s_setprio(1);
         if constexpr (HOIST && MODE == 0) {
 #pragma unroll
           for (int t = 0; t < HH; ++t)
@@ -352,6 +369,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
             }
           }
         }
+        __builtin_amdgcn_s_setprio(0);
         if constexpr (RT == 2) {
           // row k1 = 16: partial dot product over this lane group's quadrant, then
           // the four lane groups of a column (lanes j, j+16, j+32, j+48) are summed
@@ -378,7 +396,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
     for (int gi = 0; gi < NP; ++gi) {
       const int qi = gi * SLOTS + slot;
       if (qi >= nq || cell >= p.B) continue;
-      const int q1 = qb + qi;
+      const int q1 = units[ub + 2 + qi];
       T* dst = Qo + cell * p.ldq + (int64_t)q1 * NK;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {

@@ -46,7 +46,7 @@ struct wefq_core {
   double* d_R16_64 = nullptr;
   uint16_t* d_Rhi = nullptr;           // [NTm][ceil(H*H/8)][64][8] bf16 bits
   uint16_t* d_Rlo = nullptr;
-  int* d_units = nullptr;              // [nunits][3]: l1, q1 begin, count
+  int* d_units = nullptr;              // [nunits][UNIT_STRIDE]: l1, count, q1 values
   int nunits = 0;
   int GQ = 0;                          // q1 per unit
   double tile_cost = 0.0;              // estimated cost of one full 16-cell tile (scheduling only)
@@ -60,6 +60,9 @@ struct wefq_core {
 };
 
 namespace wefq {
+
+// ints per work-unit record of the apply kernels: l1, count, up to 8 q1 values
+constexpr int UNIT_STRIDE = 10;
 
 // Pad rows per q block of a 16-cell LDS tile (must match pad_rows in apply_tile.h).
 inline int tile_pad_rows(int NK, int H, int TB) { return (TB == 16 && ((NK - H) % 2) == 0) ? 1 : 0; }
