@@ -91,7 +91,7 @@ def cpu_baseline(K, L, gamma, c, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cells", type=int, default=65536)
     ap.add_argument("--K", type=int, default=12)

@@ -23,6 +23,7 @@ independent of the batch a cell lands in.
 """
 import bisect
 import math
+import sys
 import time
 
 import numpy as np
@@ -207,21 +208,26 @@ def bench(args):
     """Config 5: Poisson arrivals, 1-4096 cells (log-uniform), K = L in {8, 12, 16}, hard spheres, FP32."""
     import torch
     cfg = synth.CONFIGS[5]
+    # the library's default tile shapes (largest LDS tiles): under load, requests of one
+    # core are fused into batches of thousands of cells, where those are the fastest
     srv = make_server(torch, sizes=cfg["sizes"], pool_cells=cfg["max_cells"])
-    from . import autotune
-    for c in srv.cores:
-        autotune.tune(c, "fp32", cells=2048, reps=2)
     # warm up every core once
     for c, p in zip(srv.cores, srv.pools):
         c.apply_Q(p[:64])
     torch.cuda.synchronize()
     runs = {}
-    for rate in (250.0, 500.0, 1000.0, cfg["rate"]):
+    for rate in (250.0, 500.0, 750.0, 1000.0, 1250.0, 1500.0, cfg["rate"]):
         dur = 1.0 if rate < cfg["rate"] else 2.0
         tr = poisson_trace(rate, dur, cfg["sizes"], cfg["max_cells"], cfg["seed"] + int(rate), cfg["max_cells"])
         runs[rate] = srv.run(tr)
+        runs[rate]["trace_s"] = dur
+        print(f"[serve] rate {rate:.0f}/s: p50 {runs[rate]['p50_ms']:.1f} ms, p99 {runs[rate]['p99_ms']:.1f} ms, "
+              f"makespan {runs[rate]['makespan_s']:.2f} s", file=sys.stderr, flush=True)
     main = runs[cfg["rate"]]
-    sustainable = max([r for r, v in runs.items() if v["p99_ms"] < 1000.0 * 0.5] + [0.0])
+    # sustainable: the queue does not build up over the trace (the run ends within 0.25 s
+    # of the trace, so the device keeps pace with arrivals) and p99 stays below 250 ms
+    sustainable = max([r for r, v in runs.items()
+                       if v["makespan_s"] <= v["trace_s"] + 0.25 and v["p99_ms"] < 250.0] + [0.0])
     out = {"metric": "serving p50/p99 latency (ms) and throughput, Poisson arrivals", "value": main["p99_ms"],
            "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
@@ -229,5 +235,6 @@ def bench(args):
                       "cells_per_request": "log-uniform 1..4096", "model": "hard spheres"},
            "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"], "throughput_cells_per_s": main["throughput_cells_per_s"],
            "runs": {str(int(r)): {k: v for k, v in res.items()} for r, res in runs.items()},
-           "sustainable_rate_req_per_s_p99_below_500ms": sustainable}
+           "sustainable_rate_req_per_s": sustainable,
+           "sustainable_rule": "highest tested rate whose run ends within 0.25 s of its trace, with p99 < 250 ms"}
     return out
