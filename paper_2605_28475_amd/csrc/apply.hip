@@ -102,7 +102,7 @@ template <int H, int SLOTS, int RT, int MODE>
 __global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int unit_ctr;
-  mfma_tile<H, SLOTS, RT, MODE>(p, (int64_t)blockIdx.x, lds_raw, &unit_ctr);
+  mfma_tile<H, SLOTS, RT, MODE>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw, &unit_ctr);
 }
 
 template <int H, int SLOTS, int RT, int MODE>
@@ -110,7 +110,7 @@ static hipError_t launch_mfma_t(const MfmaParams& p, int64_t ntiles, int block, 
   auto k = apply_mfma_kernel<H, SLOTS, RT, MODE>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3((unsigned)ntiles), dim3(block), lds, s, p);
+  hipLaunchKernelGGL(k, dim3((unsigned)ntiles, (unsigned)p.nsplit), dim3(block), lds, s, p);
   return hipGetLastError();
 }
 
@@ -217,6 +217,16 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   if (slots == 0) return hipErrorInvalidValue;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
+  // Small batches: split each tile's work units over several workgroups, so that the
+  // launch still covers about two workgroups per compute unit (latency mode); every
+  // workgroup keeps at least 4 units for its 8 waves.
+  p.nsplit = 1;
+  const int64_t target = 2 * (int64_t)h->cu_count;
+  if (ntiles < target) {
+    const int64_t want = (target + ntiles - 1) / ntiles;
+    const int64_t cap = h->nunits / 4 > 1 ? h->nunits / 4 : 1;
+    p.nsplit = (int)(want < cap ? want : cap);
+  }
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   switch (h->H) {
     case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);

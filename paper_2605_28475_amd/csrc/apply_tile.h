@@ -22,6 +22,7 @@ struct MfmaParams {
   int64_t B, ldf, ldq;
   int NK, NQ, N;
   int nunits;
+  int nsplit;              // workgroups sharing one cell tile; each takes every nsplit-th unit
   const int* units;        // [nunits][UNIT_STRIDE]: l1, count, q1 values
   const int* chan_begin;   // [L+2]
   const int* slice_off;    // [NTm]
@@ -56,9 +57,11 @@ __host__ __device__ inline int pad_rows(int NK) {
   return (TB == 16 && ((NK - H) % 2) == 0) ? 1 : 0;
 }
 
-// One cell tile: stage f, then process every (l1, q1-group) work unit.
+// One cell tile: stage f, then process the (l1, q1-group) work units split, split + nsplit, ...
+// (all of them when nsplit = 1).  Each output row belongs to one unit, so splitting a tile
+// over several workgroups changes neither the work per row nor its order.
 template <int H, int SLOTS, int RT, int MODE>
-__device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, unsigned char* lds_raw,
+__device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int split, unsigned char* lds_raw,
                                           int* unit_ctr_p) {
   typedef typename ModeTraits<MODE>::T T;
   typedef typename ModeTraits<MODE>::acc_t acc_t;
@@ -127,7 +130,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, uns
   while (true) {
     int u = 0;
     if (lane == 0) u = atomicAdd(&unit_ctr, 1);
-    u = __builtin_amdgcn_readfirstlane(__shfl(u, 0));
+    u = __builtin_amdgcn_readfirstlane(__shfl(u, 0)) * p.nsplit + split;
     if (u >= p.nunits) break;
     // unit record: l1, count, then the unit's q1 values; with several output states
     // per MFMA column group, consecutive entries hold m1 and -m1, whose slices have

@@ -179,6 +179,9 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   // MFMA geometry
   h->H = (NK + 1) / 2;
   h->RT = NK > 16 ? 2 : 1;
+  if (hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess ||
+      h->cu_count <= 0)
+    h->cu_count = 256;
   int dev_lds = 0;
   if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess || dev_lds <= 0)
     dev_lds = 65536;

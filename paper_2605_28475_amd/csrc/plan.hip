@@ -41,7 +41,7 @@ __global__ void plan_reset_kernel(int* counter) {
 
 #define WEFQ_TILE_CASE(H_, S_, R_)                                       \
   case (H_) * 100 + (S_) * 10 + (R_):                                    \
-    mfma_tile<H_, S_, R_, MODE>(sd.p, tile, lds_raw, &unit_ctr);         \
+    mfma_tile<H_, S_, R_, MODE>(sd.p, tile, 0, lds_raw, &unit_ctr);      \
     break;
 #define WEFQ_TILE_CASES_H(H_) WEFQ_TILE_CASE(H_, 1, 1) WEFQ_TILE_CASE(H_, 2, 1) WEFQ_TILE_CASE(H_, 4, 1)
 
@@ -156,7 +156,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     MfmaParams& p = d.p;
     p.f = g.f; p.Q = g.Q; p.B = g.B; p.ldf = g.ld_f; p.ldq = g.ld_q;
     p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
-    p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
+    p.nunits = h->nunits; p.nsplit = 1; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
     p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.spair = h->d_spair; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
     p.mg = h->d_mg; p.mg64 = h->d_mg64;
     p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;

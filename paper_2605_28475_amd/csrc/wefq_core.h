@@ -51,6 +51,7 @@ struct wefq_core {
   int GQ = 0;                          // q1 per unit
   double tile_cost = 0.0;              // estimated cost of one full 16-cell tile (scheduling only)
   int lds_limit = 0;                   // usable LDS bytes per workgroup
+  int cu_count = 256;                  // compute units of the device
 
   // conservation check scratch
   double* d_check = nullptr;

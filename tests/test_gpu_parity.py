@@ -86,6 +86,21 @@ def test_cell_result_independent_of_batch(prec):
         assert np.array_equal(alone[0], full[b])
 
 
+@pytest.mark.parametrize("K,prec", [(12, "fp32"), (12, "fp64"), (16, "fp32"), (16, "bf16x3")])
+def test_split_tiles_bitwise_equal(K, prec):
+    """A batch large enough for one workgroup per cell tile and small batches whose tiles
+    are split over several workgroups give bitwise equal results per cell."""
+    core = gpu_core("vhs", K, K, 0.5)
+    slots, _ = core.tune_get(prec)
+    B = 512 * (16 // slots)                       # >= 2 workgroups per CU: no split
+    c = synth.perturbed_maxwellian(K, K, B, seed=123 + K)
+    say(f"[split] K={K} {prec} B={B} slots={slots}")
+    full = run(core, c, prec)
+    for lo, hi in ((0, 1), (5, 12), (B - 3, B)):
+        part = run(core, c[lo:hi], prec)
+        assert np.array_equal(part, full[lo:hi]), (lo, hi)
+
+
 def test_padded_rows_zero_batch_and_errors():
     K = L = 3
     core = gpu_core("hs", K, L, 1.0)
