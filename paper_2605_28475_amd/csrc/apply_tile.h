@@ -51,10 +51,13 @@ template <> struct ModeTraits<0> { typedef float T; typedef v4f acc_t; };
 template <> struct ModeTraits<1> { typedef float T; typedef v4f acc_t; };
 template <> struct ModeTraits<2> { typedef double T; typedef v4d acc_t; };
 
-// Pad rows per q block of the LDS tile (see the bank layout note in mfma_tile).
-template <int H, int TB>
-__host__ __device__ inline int pad_rows(int NK) {
-  return (TB == 16 && ((NK - H) % 2) == 0) ? 1 : 0;
+// Phi += u (x) w over an H x H quadrant.
+template <int H, bool INIT, typename T>
+__device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
+#pragma unroll
+  for (int a = 0; a < H; ++a)
+#pragma unroll
+    for (int b = 0; b < H; ++b) phi[a * H + b] = INIT ? u[a] * w[b] : fma(u[a], w[b], phi[a * H + b]);
 }
 
 // One cell tile: stage f, then process the (l1, q1-group) work units split, split + nsplit, ...
@@ -76,16 +79,10 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   T* Qo = static_cast<T*>(p.Q);
   const int NK = p.NK;
   const int64_t cell0 = tile * TB;
-  // Bank layout.  With 16-cell tiles an LDS row holds 16 consecutive banks, so
-  // rows of equal parity share banks; the two lane groups of a half-wave read
-  // rows NK-H apart.  When that distance is even, one zero pad row is inserted
-  // per q block between k = H-1 and k = H (the upper group then starts at
-  // NK-H+1, odd distance; for odd NK its first, duplicated row reads the pad,
-  // whose R weight is zero).
-  const int pd = pad_rows<H, TB>(NK);
+  // stage the coefficient tile: fs[(q * NKp + k + pd * (k >= H)) * TB + cell], with the
+  // zero pad and tail rows of the layout described with tile_upper_row
+  const int pd = tile_pad_rows(NK, H, TB);
   const int NKp = NK + pd;
-  const int rows = p.NQ * NKp;
-  // stage the coefficient tile: fs[(q * NKp + k + pd*(k >= H)) * TB + cell]
   for (int idx = threadIdx.x; idx < TB * p.N; idx += blockDim.x) {
     const int cl = idx / p.N, n = idx - cl * p.N;
     const int q = n / NK, k = n - q * NK;
@@ -97,7 +94,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
       const int q = idx / TB, cl = idx - q * TB;
       fs[(q * NKp + H) * TB + cl] = T(0);
     }
-  (void)rows;
+  if (tile_tail_rows(NK, H) && threadIdx.x < TB) fs[p.NQ * NKp * TB + threadIdx.x] = T(0);
   if (threadIdx.x == 0) unit_ctr = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -108,7 +105,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   // starts at 0, the upper at NK-H (for odd NK the middle row is in both halves;
   // the R tile holds zero for the copy in the upper half), so every gather is a
   // per-lane base plus a compile-time offset.
-  const int k2s = h2 ? NK - H + pd : 0, k3s = h3 ? NK - H + pd : 0;
+  const int up = tile_upper_row(NK, H, TB);
+  const int k2s = h2 ? up : 0, k3s = h3 ? up : 0;
   const T* lane_u = fs + k2s * TB + cellj;
   const T* lane_w = fs + k3s * TB + cellj;
   // read-only routing rows: through the constant address space so that
@@ -261,47 +259,109 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
             }
           }
         } else {
-          // lanes of different output states walk different slices: iterate to the
-          // longest pair and single runs of the wave, masking the shorter ones
-          const int np = (ep - e0) >> 1, ns = e1 - ep;
-          int maxp = np, maxs = ns;
+          // Lanes of different output states walk different slices.  Each slot's row
+          // range is wave-uniform, so its rows come through scalar loads and every lane
+          // keeps its own slot's row; the loops run to the longest slot, and rows past a
+          // slot's end carry weight zero and row offset 0.
+          int se0[SLOTS], sep[SLOTS], se1[SLOTS];
+          int maxp = 0, maxs = 0;
 #pragma unroll
-          for (int off = TB; off < 16; off <<= 1) {
-            const int op = __shfl_xor(maxp, off), os = __shfl_xor(maxs, off);
-            maxp = maxp > op ? maxp : op;
-            maxs = maxs > os ? maxs : os;
+          for (int sl = 0; sl < SLOTS; ++sl) {
+            const int qs = gi * SLOTS + sl;
+            se0[sl] = se1[sl] = sep[sl] = 0;
+            if (qs < nq) {
+              const int ss = soff + units[ub + 2 + qs];
+              se0[sl] = sptr[ss];
+              se1[sl] = sptr[ss + 1];
+              sep[sl] = spair[ss];
+            }
+            const int np_s = (sep[sl] - se0[sl]) >> 1, ns_s = se1[sl] - sep[sl];
+            maxp = maxp > np_s ? maxp : np_s;
+            maxs = maxs > ns_s ? maxs : ns_s;
           }
-          for (int i = 0; i < maxp; ++i) {
-            const bool in = i < np;
-            const int e = in ? e0 + 2 * i : e0;
-            const uint32_t qa = in ? mq[e] : 0u, qb = in ? mq[e + 1] : 0u;
-            const T ga = in ? (MODE == 2 ? (T)mg64[e] : (T)mg[e]) : T(0);
-            const T gb = in ? (MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1]) : T(0);
-            const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
-            const T* pa = lane_w + (int)(qa >> 16) * TB;
-            const T* pb = lane_w + (int)(qb >> 16) * TB;
-            T fu[H], ww[H];
+          auto fetch_pair = [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            qa = qb = 0u;
+            ga = gb = T(0);
 #pragma unroll
-            for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; ww[a] = fma(gb, pb[a * TB], ga * pa[a * TB]); }
+            for (int sl = 0; sl < SLOTS; ++sl) {
+              if (i < ((sep[sl] - se0[sl]) >> 1)) {
+                const int e = se0[sl] + 2 * i;
+                const uint32_t xa = mq[e], xb = mq[e + 1];
+                const T ya = MODE == 2 ? (T)mg64[e] : (T)mg[e];
+                const T yb = MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1];
+                if (slot == sl) { qa = xa; qb = xb; ga = ya; gb = yb; }
+              }
+            }
+          };
+          auto fetch_single = [&](int i, uint32_t& qq, T& gg) {
+            qq = 0u;
+            gg = T(0);
 #pragma unroll
-            for (int a = 0; a < H; ++a)
+            for (int sl = 0; sl < SLOTS; ++sl) {
+              if (i < se1[sl] - sep[sl]) {
+                const int e = sep[sl] + i;
+                const uint32_t x = mq[e];
+                const T y = MODE == 2 ? (T)mg64[e] : (T)mg[e];
+                if (slot == sl) { qq = x; gg = y; }
+              }
+            }
+          };
+          if (maxp > 0) {
+            uint32_t qa, qb;
+            T ga, gb, fu[H], fa[H], fb[H];
+            fetch_pair(0, qa, qb, ga, gb);
+            {
+              const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
+              const T* pa = lane_w + (int)(qa >> 16) * TB;
+              const T* pb = lane_w + (int)(qb >> 16) * TB;
 #pragma unroll
-              for (int b = 0; b < H; ++b) phi[a * H + b] = fma(fu[a], ww[b], phi[a * H + b]);
+              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fa[a] = pa[a * TB]; fb[a] = pb[a * TB]; }
+            }
+            for (int i = 0; i < maxp; ++i) {
+              uint32_t qna, qnb;
+              T gna, gnb, nu[H], na[H], nb[H];
+              fetch_pair(i + 1, qna, qnb, gna, gnb);
+              const T* pu = lane_u + (int)(qna & 0xffffu) * TB;
+              const T* pa = lane_w + (int)(qna >> 16) * TB;
+              const T* pb = lane_w + (int)(qnb >> 16) * TB;
+#pragma unroll
+              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; na[a] = pa[a * TB]; nb[a] = pb[a * TB]; }
+              T ww[H];
+#pragma unroll
+              for (int b = 0; b < H; ++b) ww[b] = fma(gb, fb[b], ga * fa[b]);
+              outer_product<H, false>(phi, fu, ww);
+#pragma unroll
+              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fa[a] = na[a]; fb[a] = nb[a]; }
+              ga = gna;
+              gb = gnb;
+            }
           }
-          for (int i = 0; i < maxs; ++i) {
-            const bool in = i < ns;
-            const int e = in ? ep + i : e0;
-            const uint32_t qq = in ? mq[e] : 0u;
-            const T gg = in ? (MODE == 2 ? (T)mg64[e] : (T)mg[e]) : T(0);
-            const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
-            const T* pw = lane_w + (int)(qq >> 16) * TB;
-            T uu[H], ww[H];
+          if (maxs > 0) {
+            uint32_t qq;
+            T gg, fu[H], fw[H];
+            fetch_single(0, qq, gg);
+            {
+              const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
+              const T* pw = lane_w + (int)(qq >> 16) * TB;
 #pragma unroll
-            for (int a = 0; a < H; ++a) { uu[a] = gg * pu[a * TB]; ww[a] = pw[a * TB]; }
+              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fw[a] = pw[a * TB]; }
+            }
+            for (int i = 0; i < maxs; ++i) {
+              uint32_t qn;
+              T gn, nu[H], nw[H];
+              fetch_single(i + 1, qn, gn);
+              const T* pu = lane_u + (int)(qn & 0xffffu) * TB;
+              const T* pw = lane_w + (int)(qn >> 16) * TB;
 #pragma unroll
-            for (int a = 0; a < H; ++a)
+              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; nw[a] = pw[a * TB]; }
+              T uu[H];
 #pragma unroll
-              for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], ww[b], phi[a * H + b]);
+              for (int a = 0; a < H; ++a) uu[a] = gg * fu[a];
+              outer_product<H, false>(phi, uu, fw);
+#pragma unroll
+              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fw[a] = nw[a]; }
+              gg = gn;
+            }
           }
         }
         // Radial contraction of the slice on the matrix cores.  The wave raises its

@@ -210,14 +210,16 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     h->block[mode] = 512;
   }
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;   // RT == 2: NK = 17
-  // A-operand value for lane group r at step t: the group's quadrant starts at
-  // 0 (lower half) or NK-H (upper half); a row or column that the upper half
-  // shares with the lower half (odd NK) is counted by the lower half only.
+  // A-operand value for lane group r at step t: the group's quadrant starts at k = 0
+  // (lower half) or k = tile_upper_k (upper half); upper-half rows outside [H, NK), the
+  // one shared with the lower half or the one past the end, have zero weight.
+  const int uk = tile_upper_k(NK, H);
   auto Rval = [&](int m, int k1, int t, int r) -> double {
     if (t >= HH || k1 >= NK) return 0.0;
     int a = t / H, b = t % H;
     int h2 = r >> 1, h3 = r & 1;
-    int k2 = (h2 ? NK - H : 0) + a, k3 = (h3 ? NK - H : 0) + b;
+    int k2 = (h2 ? uk : 0) + a, k3 = (h3 ? uk : 0) + b;
+    if (k2 >= NK || k3 >= NK) return 0.0;
     if (h2 && k2 < H) return 0.0;
     if (h3 && k3 < H) return 0.0;
     return Rm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3];

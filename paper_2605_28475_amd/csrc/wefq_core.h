@@ -65,8 +65,26 @@ namespace wefq {
 // ints per work-unit record of the apply kernels: l1, count, up to 8 q1 values
 constexpr int UNIT_STRIDE = 10;
 
-// Pad rows per q block of a 16-cell LDS tile (must match pad_rows in apply_tile.h).
-inline int tile_pad_rows(int NK, int H, int TB) { return (TB == 16 && ((NK - H) % 2) == 0) ? 1 : 0; }
+// LDS layout of a cell tile (shared by the host tables and the kernels).  Rows are
+// (q, k), TB cells per row, one block of NK rows per q.  Lane groups of the lower half
+// of k read rows [0, H) of a block, those of the upper half H rows from `upper`.  The two
+// halves start an odd number of rows apart, so that rows of 16, 8 or 4 cells read by
+// the two halves fall into different LDS banks:
+//  * odd NK, odd H: the upper half starts at k = H; its last row (k = NK) has zero
+//    weight and reads the next block's first row, or after the last block one zero
+//    tail row;
+//  * odd NK, even H: it starts at k = NK - H = H - 1; that first row, shared with the
+//    lower half, has zero weight;
+//  * even NK: it starts at k = H; when H is even and TB = 16, one zero pad row per block
+//    sits between k = H - 1 and k = H.
+__host__ __device__ inline int tile_pad_rows(int NK, int H, int TB) {
+  return (TB == 16 && !(NK & 1) && !(H & 1)) ? 1 : 0;
+}
+__host__ __device__ inline int tile_tail_rows(int NK, int H) { return ((NK & 1) && (H & 1)) ? 1 : 0; }
+__host__ __device__ inline int tile_upper_k(int NK, int H) { return ((NK & 1) && !(H & 1)) ? NK - H : H; }
+__host__ __device__ inline int tile_upper_row(int NK, int H, int TB) {
+  return tile_upper_k(NK, H) + tile_pad_rows(NK, H, TB);
+}
 
 // Kernel mode of a precision: 0 FP32, 1 BF16X3, 2 FP64 (tiled); -1 otherwise.
 inline int mfma_mode(int precision) {
@@ -77,7 +95,7 @@ inline int mfma_mode(int precision) {
 inline size_t tile_lds_bytes(const wefq_core* h, int slots, size_t elem) {
   const int TB = 16 / slots;
   const int pd = tile_pad_rows(h->NK, h->H, TB);
-  return (size_t)h->NQ * (h->NK + pd) * TB * elem;
+  return ((size_t)h->NQ * (h->NK + pd) + tile_tail_rows(h->NK, h->H)) * TB * elem;
 }
 
 // Error reporting helper (thread-local message).
