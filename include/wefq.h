@@ -141,8 +141,10 @@ typedef struct {
   int64_t B, ld_f, ld_q;
 } wefq_segment;
 
-/* Build a plan: one work item per (segment, cell tile), largest first, served by a
- * persistent kernel whose workgroups pull items from a device counter; the counter
+/* Build a plan: one work item per (segment, cell tile), or several per tile when a tile
+ * costs more than a third of a workgroup's fair share of the plan (each then takes every
+ * n-th work unit of the tile), largest first, served by a persistent kernel whose
+ * workgroups pull items from a device counter; the counter
  * reset and the kernel are captured once in a HIP graph.  Per-cell results equal
  * those of wefq_apply_Q bitwise.  Buffers and cores must outlive the plan; the plan
  * owns a small device work list.  Synchronizes stream. */

@@ -2,8 +2,10 @@
 // collision model in one kernel), captured once in a HIP graph.
 //
 // A plan is a list of segments (core, precision, f, Q, B, tile shape).  Its
-// work list holds one item per (segment, cell tile), sorted by decreasing
-// estimated cost, so the largest tiles start first.  The persistent kernel
+// work list holds one item per (segment, cell tile), or several per tile when a
+// tile's cost exceeds a third of a workgroup's fair share (the tile's work units
+// are then dealt round-robin to the items), sorted by decreasing estimated cost,
+// so the largest items start first and the last ones are short.  The persistent kernel
 // runs as many workgroups as fit on the device at once; each pulls items from
 // a device counter and runs the same per-tile code as the standalone apply
 // (same arithmetic order, hence bitwise the same per-cell results), selecting
@@ -12,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -30,7 +33,7 @@ struct SegDesc {
 
 struct PlanParams {
   const SegDesc* segs;
-  const int64_t* items;     // seg << 40 | tile
+  const int64_t* items;     // seg << 48 | split << 40 | tile
   int nitems;
   int* counter;
 };
@@ -41,7 +44,7 @@ __global__ void plan_reset_kernel(int* counter) {
 
 #define WEFQ_TILE_CASE(H_, S_, R_)                                       \
   case (H_) * 100 + (S_) * 10 + (R_):                                    \
-    mfma_tile<H_, S_, R_, MODE>(sd.p, tile, 0, lds_raw, &unit_ctr);      \
+    mfma_tile<H_, S_, R_, MODE>(sd.p, tile, split, lds_raw, &unit_ctr);  \
     break;
 #define WEFQ_TILE_CASES_H(H_) WEFQ_TILE_CASE(H_, 1, 1) WEFQ_TILE_CASE(H_, 2, 1) WEFQ_TILE_CASE(H_, 4, 1)
 
@@ -57,7 +60,8 @@ __global__ __launch_bounds__(512) void apply_persistent_kernel(PlanParams pp) {
     __syncthreads();
     if (it >= pp.nitems) break;
     const int64_t code = pp.items[it];
-    const SegDesc& sd = pp.segs[(int)(code >> 40)];
+    const SegDesc& sd = pp.segs[(int)(code >> 48)];
+    const int split = (int)((code >> 40) & 0xff);
     const int64_t tile = code & ((1LL << 40) - 1);
     switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
       WEFQ_TILE_CASES_H(1) WEFQ_TILE_CASES_H(2) WEFQ_TILE_CASES_H(3)
@@ -131,8 +135,11 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
   const int mode = prec == WEFQ_FP64 ? 2 : (prec == WEFQ_BF16X3 ? 1 : 0);
   const size_t elem = mode == 2 ? 8 : 4;
   const int device = segs[0].core ? segs[0].core->device : -1;
+  if (nseg >= (1 << 15)) return plan_fail(WEFQ_EINVAL, "too many segments");
   std::vector<SegDesc> descs(nseg);
-  std::vector<std::pair<double, int64_t>> items;
+  std::vector<int64_t> seg_tiles(nseg);
+  std::vector<double> seg_cost(nseg);
+  std::vector<int> seg_units(nseg);
   size_t lds = 0;
   for (int i = 0; i < nseg; ++i) {
     const wefq_segment& g = segs[i];
@@ -164,13 +171,39 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     d.H = h->H; d.SLOTS = slots; d.RT = h->RT;
     const int64_t ntiles = (g.B + TB - 1) / TB;
     if (ntiles >= (1LL << 40)) return plan_fail(WEFQ_EINVAL, "segment too large");
-    const double cost = h->tile_cost * (double)TB / 16.0;
-    for (int64_t t = 0; t < ntiles; ++t) items.push_back({cost, ((int64_t)i << 40) | t});
+    seg_tiles[i] = ntiles;
+    seg_cost[i] = h->tile_cost * (double)TB / 16.0;
+    seg_units[i] = h->nunits;
+  }
+  if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
+  const void* k = mode == 0 ? (const void*)apply_persistent_kernel<0>
+                  : mode == 1 ? (const void*)apply_persistent_kernel<1> : (const void*)apply_persistent_kernel<2>;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
+  // Work items: (segment, cell tile, split), largest first.  A tile whose cost exceeds a
+  // third of a workgroup's fair share is split over several workgroups (its work units
+  // dealt round-robin, as in a small-batch launch), so that the last items are short.
+  double total = 0.0;
+  for (int i = 0; i < nseg; ++i) total += seg_cost[i] * (double)seg_tiles[i];
+  const double target = total / (3.0 * (double)per_cu * (double)cus);
+  std::vector<std::pair<double, int64_t>> items;
+  for (int i = 0; i < nseg; ++i) {
+    int ns = 1;
+    if (target > 0.0 && seg_cost[i] > target) {
+      const int cap = std::max(1, std::min(255, seg_units[i] / 4));
+      ns = (int)std::min<double>(cap, std::ceil(seg_cost[i] / target));
+    }
+    descs[i].p.nsplit = ns;
+    for (int64_t t = 0; t < seg_tiles[i]; ++t)
+      for (int sp = 0; sp < ns; ++sp)
+        items.push_back({seg_cost[i] / ns, ((int64_t)i << 48) | ((int64_t)sp << 40) | t});
   }
   if (items.size() > 0x7fffffffULL) return plan_fail(WEFQ_EINVAL, "too many work items");
   std::stable_sort(items.begin(), items.end(),
                    [](const std::pair<double, int64_t>& a, const std::pair<double, int64_t>& b) { return a.first > b.first; });
-  if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
   wefq_plan_s* pl = new (std::nothrow) wefq_plan_s();
   if (!pl) return plan_fail(WEFQ_ENOMEM, "host allocation failed");
   pl->device = device; pl->mode = mode; pl->block = block; pl->lds = lds; pl->nitems = (int)items.size();
@@ -186,16 +219,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
                                         hipMemcpyHostToDevice, s) == hipSuccess) &&
        hipStreamSynchronize(s) == hipSuccess;
   if (!ok) { plan_free(pl); return plan_fail(WEFQ_EHIP, "plan upload failed"); }
-  const void* k = mode == 0 ? (const void*)apply_persistent_kernel<0>
-                  : mode == 1 ? (const void*)apply_persistent_kernel<1> : (const void*)apply_persistent_kernel<2>;
   pl->kernel = k;
-  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
-    plan_free(pl);
-    return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
-  }
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
   pl->grid = std::max(1, std::min(per_cu * cus, std::max(1, pl->nitems)));
   // capture {reset, persistent kernel} once; replays launch the instantiated graph
   hipStream_t cs = nullptr;

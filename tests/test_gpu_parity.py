@@ -67,6 +67,27 @@ def test_apply_matches_oracle(K, L, model, gamma, B, prec):
     assert np.all(q[:, invariant_indices(K, L)] == 0.0)
 
 
+@pytest.mark.parametrize("K", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("slots", [1, 2, 4])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_tile_shapes_match_oracle(K, slots, prec):
+    """Every LDS tile layout (odd NK with odd or even H, even NK with or without pad rows)
+    at 16-, 8- and 4-cell tiles, against the oracle; the shape is restored afterwards."""
+    L = 4
+    core = gpu_core("vhs", K, L, 0.5)
+    old = core.tune_get(prec)
+    say(f"[tiles] K={K} L={L} slots={slots} {prec}")
+    core.tune_set(prec, slots, old[1])
+    try:
+        c = synth.perturbed_maxwellian(K, L, 23, seed=synth.BASE_SEED + 7 * K + slots)
+        ref = oapply.apply_q(core_zeroed(K, L, 0.5), coo(L), c, K)
+        q = run(core, c, prec)
+    finally:
+        core.tune_set(prec, *old)
+    assert rel_err(q, ref) < TOL[prec]
+    assert np.all(q[:, invariant_indices(K, L)] == 0.0)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp64_naive", "fp32", "bf16x3"])
 def test_unit_maxwellian_is_exact_fixed_point(prec):
     K = L = 4
