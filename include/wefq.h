@@ -109,7 +109,9 @@ wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* 
 
 /* FP64 check of the five collision-invariant rows (Section 4.4) of a computed Q:
  * *max_abs = max over cells of |Q| on those rows (exactly 0 when conservation
- * holds).  Synchronizes stream. */
+ * holds; NaN if any of them is NaN).  Q as for wefq_apply_Q with the same precision.
+ * Synchronizes stream.  The per-block partial maxima go to a small device buffer
+ * owned by the handle, so checks on one handle must not run concurrently. */
 wefq_status wefq_check_conservation(wefq_handle h, int32_t precision, const void* Q,
                                     int64_t B, int64_t ld_q, double* max_abs, void* stream);
 
@@ -157,6 +159,36 @@ wefq_status wefq_plan_launch(wefq_plan p, void* stream);
 wefq_status wefq_plan_launch_direct(wefq_plan p, void* stream);
 wefq_status wefq_plan_info(wefq_plan p, int64_t* work_items, int64_t* lds_bytes, int64_t* grid);
 wefq_status wefq_plan_destroy(wefq_plan p);
+
+/* ---- time integration: batched explicit Runge-Kutta stepping of dc/dt = Q(c) ---- */
+
+/* With the identity mass matrix the Galerkin weak form is an ODE system per cell
+ * (Section 2.3); the relaxation experiments of Section 5 integrate it with an
+ * explicit Runge-Kutta scheme.  Schemes: forward Euler, Heun (2 stages), the
+ * three-stage strong-stability-preserving scheme, and the classic four-stage one. */
+typedef enum {
+  WEFQ_RK_EULER = 1,
+  WEFQ_RK_HEUN = 2,
+  WEFQ_RK_SSP3 = 3,
+  WEFQ_RK_CLASSIC4 = 4
+} wefq_rk_scheme;
+
+/* Device workspace (bytes) that wefq_rk_integrate needs for B cells: 256 bytes of
+ * check state plus (stages + 1) compact [B][N] buffers of the precision's element. */
+wefq_status wefq_rk_workspace(wefq_handle h, int32_t precision, int32_t scheme, int64_t B, int64_t* bytes);
+
+/* Advance the device coefficients c ([B][ld], ld >= N, element as for wefq_apply_Q)
+ * in place by nsteps steps of size dt of the given scheme.  Every stage evaluates Q
+ * with wefq_apply_Q's kernels on the whole batch, followed by fused element-wise
+ * combinations.  work is a caller-owned device buffer of at least wefq_rk_workspace
+ * bytes, 256-byte aligned, not overlapping c; nothing is allocated.  When max_invariant
+ * is not NULL it receives the FP64 maximum of |Q| over the five invariant rows of every
+ * stage evaluation (exactly 0 when conservation holds; then the invariant coefficients
+ * of c are unchanged bit for bit), and the call synchronizes stream; otherwise it is
+ * asynchronous.  Per-cell results do not depend on the batch. */
+wefq_status wefq_rk_integrate(wefq_handle h, int32_t precision, int32_t scheme, void* c, int64_t B, int64_t ld,
+                              double dt, int32_t nsteps, void* work, int64_t work_bytes, double* max_invariant,
+                              void* stream);
 
 /* ---- host-only helpers (no device needed), used to test the host tables ---- */
 

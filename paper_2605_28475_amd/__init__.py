@@ -10,10 +10,12 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import BF16X3, FP32, FP64, FP64_NAIVE, HARD_SPHERE, MAXWELL, VHS, WefqError
+from ._lib import (BF16X3, FP32, FP64, FP64_NAIVE, HARD_SPHERE, MAXWELL, RK_CLASSIC4, RK_EULER, RK_HEUN,
+                   RK_SSP3, VHS, WefqError)
 
 MODELS = {"maxwell": MAXWELL, "mm": MAXWELL, "hard_sphere": HARD_SPHERE, "hs": HARD_SPHERE, "vhs": VHS}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp64_naive": FP64_NAIVE}
+RK_SCHEMES = {"euler": RK_EULER, "heun": RK_HEUN, "ssp3": RK_SSP3, "rk4": RK_CLASSIC4}
 
 
 def num_modes(K, L):
@@ -93,6 +95,35 @@ class Core:
                                                       Q2.stride(0) if Q2.shape[0] > 1 else Q2.shape[1],
                                                       ctypes.byref(res), _stream_ptr(stream, Q2.device)))
         return res.value
+
+    def rk_workspace_bytes(self, B, scheme="rk4", precision="fp32"):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        n = ctypes.c_int64()
+        _lib.check(_lib.lib().wefq_rk_workspace(self._h, prec, RK_SCHEMES.get(scheme, scheme), int(B), ctypes.byref(n)))
+        return n.value
+
+    def rk_integrate(self, c, dt, nsteps, scheme="rk4", precision=None, work=None, check=True, stream=None):
+        """Advance the [B, N] device tensor c in place by nsteps explicit Runge-Kutta steps
+        of dc/dt = Q(c) (wefq_rk_integrate).  work: optional uint8 device tensor of at least
+        rk_workspace_bytes(B) bytes (allocated here when None).  Returns the FP64 maximum of
+        |Q| over the invariant rows of every stage evaluation when check is true."""
+        import torch
+        c2 = c.unsqueeze(0) if c.dim() == 1 else c
+        prec = self._prec(c2, precision)
+        want = torch.float64 if prec in (FP64, FP64_NAIVE) else torch.float32
+        if c2.dtype != want or c2.device.type != "cuda" or c2.stride(-1) != 1:
+            raise ValueError(f"c must be a CUDA {want} tensor with unit stride in the last dimension")
+        B = c2.shape[0]
+        sch = RK_SCHEMES.get(scheme, scheme)
+        need = self.rk_workspace_bytes(B, sch, prec)
+        if work is None:
+            work = torch.empty(need, dtype=torch.uint8, device=c2.device)
+        res = ctypes.c_double()
+        _lib.check(_lib.lib().wefq_rk_integrate(self._h, prec, int(sch), ctypes.c_void_p(c2.data_ptr()), B,
+                                                c2.stride(0) if B > 1 else c2.shape[1], float(dt), int(nsteps),
+                                                ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                                ctypes.byref(res) if check else None, _stream_ptr(stream, c2.device)))
+        return res.value if check else None
 
     def tune_set(self, precision, slots, block):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)

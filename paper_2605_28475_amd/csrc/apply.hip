@@ -4,25 +4,29 @@
 //                     (eq. full_discrete_sum as written), one thread per output
 //                     (cell, q1, k1), looping over the COO rows of q1 and k2, k3;
 //                     no channel merging, no tiling, no matrix cores.
-// apply_mfma_kernel   angular-first contraction (Section 4.5.4) re-laid for CDNA4:
-//   * a workgroup owns a tile of 16 cells (8 when f does not fit in LDS; then
-//     the 16 MFMA columns are 8 cells x 2 output states) and stages their
-//     coefficients in LDS as fs[n][cell];
+// apply_mfma_kernel   angular-first contraction (Section 4.5.4) re-laid for CDNA4
+//                     (the per-tile code is mfma_tile in apply_tile.h):
+//   * a workgroup owns a tile of 16 cells (8 or 4 when f does not fit in LDS; then
+//     the 16 MFMA columns are 8 cells x 2 or 4 cells x 4 output states) and stages
+//     their coefficients in LDS, rows (q, k) by cells;
 //   * the COO rows (q1,q2,q3) and (q1,q3,q2) are merged (exact for Q(f,f)), so
 //     channel (l1,l2,l3) with l2 < l3 carries R^{(l1l2l3)}_{k1k2k3} + R^{(l1l3l2)}_{k1k3k2};
 //   * per slice (channel, q1) the intermediate Phi^{(c,q1)}_{k2k3} =
-//     sum_z g_z f_{k2,q2z} f_{k3,q3z} (angular coupling, FP32 VALU) is built by
+//     sum_z g_z f_{k2,q2z} f_{k3,q3z} (angular coupling, on the VALU) is built by
 //     wave-uniform integer-indexed gathers from LDS straight into the MFMA
 //     B-operand layout: lane group r = lane/16 owns the (k2,k3) quadrant
-//     (r/2, r%2) of the NK x NK grid, lane%16 is the MFMA column (cell);
+//     (r/2, r%2) of the NK x NK grid, lane%16 is the MFMA column (cell); rows
+//     sharing q2 are applied in pairs, one outer product per pair;
 //   * the radial contraction Q_{k1,q1} += sum R^{(c)}_{k1,(k2k3)} Phi_{(k2k3)}
-//     runs on v_mfma_f32_16x16x4_f32 (FP32) or as three split hi/lo BF16
-//     v_mfma_f32_16x16x32_bf16 products with FP32 accumulation (BF16X3);
+//     runs on v_mfma_f32_16x16x4_f32 (FP32), v_mfma_f64_16x16x4_f64 (FP64) or as
+//     three split hi/lo BF16 v_mfma_f32_16x16x32_bf16 products with FP32
+//     accumulation (BF16X3); for NK = 17 the last radial row is a VALU dot product;
 //   * the wave keeps the 16x16 accumulator tiles of a group of q1 values of
 //     one l1 across all channels of that l1 (the channel reduction), so every
 //     output is produced by one wave in a fixed order: results are bitwise
 //     independent of the other cells in the batch;
-//   * waves pull (l1, q1-group) work units from an LDS counter, largest first.
+//   * waves pull (l1, q1-group) work units from an LDS counter, largest first; a
+//     launch with few tiles deals each tile's units to several workgroups.
 // The mass, momentum and energy rows are stored as exact zeros (Section 4.4).
 #include <hip/hip_runtime.h>
 
@@ -252,8 +256,8 @@ __global__ void check_kernel(const void* Q, int precision, int64_t B, int64_t ld
   if (L >= 1) { rows[nrows] = NK; rows[nrows + 1] = 2 * NK; rows[nrows + 2] = 3 * NK; nrows += 3; }
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += (int64_t)gridDim.x * blockDim.x) {
     for (int i = 0; i < nrows; ++i) {
-      double v = (precision == 1 || precision == 8) ? ((const double*)Q)[b * ldq + rows[i]]
-                                : (double)((const float*)Q)[b * ldq + rows[i]];
+      double v = (precision == WEFQ_FP64 || precision == WEFQ_FP64_NAIVE) ? ((const double*)Q)[b * ldq + rows[i]]
+                                                                           : (double)((const float*)Q)[b * ldq + rows[i]];
       v = fabs(v);
       m = (v > m || v != v) ? v : m;
     }

@@ -32,15 +32,15 @@ struct MfmaParams {
   const uint32_t* mq_pad;  // the same with the padded row pitch (16-cell tiles with a pad row)
   const float* mg;         // merged weights (FP32 / BF16X3)
   const double* mg64;      // merged weights (FP64)
-  const float* Rt32;       // [NTm][RT][H*H][64]
-  const double* Rt64;      // [NTm][RT][H*H][64]
+  const float* Rt32;       // [NTm][H*H][64]: rows k1 < 16 in the MFMA A-operand layout
+  const double* Rt64;      // [NTm][H*H][64]
   const uint16_t* Rhi;     // [NTm][U][64][8]
   const uint16_t* Rlo;
   const float* R16_32;     // NK = 17 only: row k1 = 16 of R per lane group, [NTm][4][H*H]
   const double* R16_64;
 };
 
-// output states per work unit (fewer when NK > 16 needs two accumulator row tiles)
+// output states per work unit (fewer for 8x8 and 9x9 quadrants, where registers are scarce)
 __host__ __device__ constexpr int gq_for(int H) { return H >= 8 ? 4 : 8; }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -52,12 +52,12 @@ template <> struct ModeTraits<1> { typedef float T; typedef v4f acc_t; };
 template <> struct ModeTraits<2> { typedef double T; typedef v4d acc_t; };
 
 // Phi += u (x) w over an H x H quadrant.
-template <int H, bool INIT, typename T>
+template <int H, typename T>
 __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
 #pragma unroll
   for (int a = 0; a < H; ++a)
 #pragma unroll
-    for (int b = 0; b < H; ++b) phi[a * H + b] = INIT ? u[a] * w[b] : fma(u[a], w[b], phi[a * H + b]);
+    for (int b = 0; b < H; ++b) phi[a * H + b] = fma(u[a], w[b], phi[a * H + b]);
 }
 
 // One cell tile: stage f, then process the (l1, q1-group) work units split, split + nsplit, ...
@@ -101,10 +101,10 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   const int r = lane >> 4, j = lane & 15;
   const int h2 = r >> 1, h3 = r & 1;
   const int cellj = j % TB, slot = j / TB;
-  // lane group r covers k2 in [k2s, k2s+H) and k3 in [k3s, k3s+H): the lower half
-  // starts at 0, the upper at NK-H (for odd NK the middle row is in both halves;
-  // the R tile holds zero for the copy in the upper half), so every gather is a
-  // per-lane base plus a compile-time offset.
+  // lane group r covers the rows [k2s, k2s+H) for k2 and [k3s, k3s+H) for k3 of every
+  // q block: the lower half starts at row 0, the upper half at tile_upper_row (the R
+  // tile gives zero weight to its rows outside [H, NK)), so every gather is a per-lane
+  // base plus a compile-time offset.
   const int up = tile_upper_row(NK, H, TB);
   const int k2s = h2 ? up : 0, k3s = h3 ? up : 0;
   const T* lane_u = fs + k2s * TB + cellj;
@@ -136,10 +136,10 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
     const int ub = UNIT_STRIDE * u;
     const int l1 = units[ub], nq = units[ub + 1];
     // RT == 2 marks NK = 17: rows 0..15 on MFMA, row 16 as a VALU dot product
-    acc_t acc[NP][1];
+    acc_t acc[NP];
     T acc16[NP];
 #pragma unroll
-    for (int gi = 0; gi < NP; ++gi) { acc[gi][0] = (acc_t){0, 0, 0, 0}; acc16[gi] = T(0); }
+    for (int gi = 0; gi < NP; ++gi) { acc[gi] = (acc_t){0, 0, 0, 0}; acc16[gi] = T(0); }
     const int cb = chan_begin[l1], ce = chan_begin[l1 + 1];
     for (int ct = cb; ct < ce; ++ct) {
       const int soff = slice_off[ct] - l1 * l1;
@@ -169,27 +169,15 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
 #pragma unroll
       for (int gi = 0; gi < NP; ++gi) {
         if (gi * SLOTS >= nq) break;
-        const int qi = gi * SLOTS + slot;
-        const bool qvalid = qi < nq;
-        int q1s = units[ub + 2 + gi * SLOTS];
-#pragma unroll
-        for (int sl = 1; sl < SLOTS; ++sl)
-          if (slot == sl && gi * SLOTS + sl < nq) q1s = units[ub + 2 + gi * SLOTS + sl];
-        const int s = soff + q1s;
-        int e0 = sptr[s], e1 = sptr[s + 1];
-        if (!qvalid) e1 = e0;
         T phi[U * 8];
 #pragma unroll
         for (int t = 0; t < U * 8; ++t) phi[t] = T(0);
         // The slice's rows come as pairs sharing q2, then single rows.  A pair adds
         // f_{k2,q2} (g_a f_{k3,q3a} + g_b f_{k3,q3b}) to Phi: one outer product for
         // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.
-        int ep = spair[s];
-        if (!qvalid) ep = e0;
-        if (SLOTS == 1) {               // the slice is shared by the whole wave
-          e0 = __builtin_amdgcn_readfirstlane(e0);
-          e1 = __builtin_amdgcn_readfirstlane(e1);
-          ep = __builtin_amdgcn_readfirstlane(ep);
+        if constexpr (SLOTS == 1) {     // the slice is shared by the whole wave
+          const int s = soff + units[ub + 2 + gi];
+          const int e0 = sptr[s], e1 = sptr[s + 1], ep = spair[s];
           // software pipeline: the gathers of the next row (pair) are in flight
           // while the outer product of the current one accumulates (the arrays
           // carry tail slack, whose row offsets point at LDS row 0)
@@ -329,7 +317,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
               T ww[H];
 #pragma unroll
               for (int b = 0; b < H; ++b) ww[b] = fma(gb, fb[b], ga * fa[b]);
-              outer_product<H, false>(phi, fu, ww);
+              outer_product<H>(phi, fu, ww);
 #pragma unroll
               for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fa[a] = na[a]; fb[a] = nb[a]; }
               ga = gna;
@@ -357,7 +345,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
               T uu[H];
 #pragma unroll
               for (int a = 0; a < H; ++a) uu[a] = gg * fu[a];
-              outer_product<H, false>(phi, uu, fw);
+              outer_product<H>(phi, uu, fw);
 #pragma unroll
               for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fw[a] = nw[a]; }
               gg = gn;
@@ -373,42 +361,34 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
         if constexpr (HOIST && MODE == 0) {
 #pragma unroll
           for (int t = 0; t < HH; ++t)
-            acc[gi][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[t], phi[t], acc[gi][0], 0, 0, 0);
+            acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(a32[t], phi[t], acc[gi], 0, 0, 0);
         } else if constexpr (HOIST && MODE == 2) {
 #pragma unroll
           for (int t = 0; t < HH; ++t)
-            acc[gi][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[t], phi[t], acc[gi][0], 0, 0, 0);
+            acc[gi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[t], phi[t], acc[gi], 0, 0, 0);
         } else if constexpr (MODE == 0) {
+          const float* At = p.Rt32 + ((int64_t)ct * HH) * 64 + lane;
 #pragma unroll
-          for (int rt = 0; rt < 1; ++rt) {
-            const float* At = p.Rt32 + ((int64_t)ct * HH) * 64 + lane;
+          for (int t0 = 0; t0 < HH; t0 += 8) {
+            float av[8];
 #pragma unroll
-            for (int t0 = 0; t0 < HH; t0 += 8) {
-              float av[8];
+            for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0f;
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-              for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0f;
-              __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-              for (int t = 0; t < 8; ++t)
-                if (t0 + t < HH)
-                  acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], phi[t0 + t], acc[gi][rt], 0, 0, 0);
-            }
+            for (int t = 0; t < 8; ++t)
+              if (t0 + t < HH) acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], phi[t0 + t], acc[gi], 0, 0, 0);
           }
         } else if constexpr (MODE == 2) {
+          const double* At = p.Rt64 + ((int64_t)ct * HH) * 64 + lane;
 #pragma unroll
-          for (int rt = 0; rt < 1; ++rt) {
-            const double* At = p.Rt64 + ((int64_t)ct * HH) * 64 + lane;
+          for (int t0 = 0; t0 < HH; t0 += 8) {
+            double av[8];
 #pragma unroll
-            for (int t0 = 0; t0 < HH; t0 += 8) {
-              double av[8];
+            for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0;
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-              for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0;
-              __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-              for (int t = 0; t < 8; ++t)
-                if (t0 + t < HH)
-                  acc[gi][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], phi[t0 + t], acc[gi][rt], 0, 0, 0);
-            }
+            for (int t = 0; t < 8; ++t)
+              if (t0 + t < HH) acc[gi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], phi[t0 + t], acc[gi], 0, 0, 0);
           }
         } else {
 #pragma unroll
@@ -421,15 +401,12 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
               bh[e] = xh;
               bl[e] = (__bf16)(x - (float)xh);
             }
-#pragma unroll
-            for (int rt = 0; rt < 1; ++rt) {
-              const int64_t off = (((int64_t)ct * U + uu8) * 64 + lane) * 8;
-              const v8bf ah = HOIST ? ahi[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rhi + off);
-              const v8bf al = HOIST ? alo[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rlo + off);
-              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[gi][rt], 0, 0, 0);
-              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[gi][rt], 0, 0, 0);
-              acc[gi][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[gi][rt], 0, 0, 0);
-            }
+            const int64_t off = (((int64_t)ct * U + uu8) * 64 + lane) * 8;
+            const v8bf ah = HOIST ? ahi[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rhi + off);
+            const v8bf al = HOIST ? alo[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rlo + off);
+            acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[gi], 0, 0, 0);
+            acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[gi], 0, 0, 0);
+            acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[gi], 0, 0, 0);
           }
         }
         __builtin_amdgcn_s_setprio(0);
@@ -464,7 +441,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int k1 = MODE == 2 ? r + 4 * i : 4 * r + i;
-        if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? T(0) : (T)acc[gi][0][i];
+        if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? T(0) : (T)acc[gi][i];
       }
       if (RT == 2 && r == 0) dst[16] = acc16[gi];
     }

@@ -88,6 +88,19 @@ def test_tile_shapes_match_oracle(K, slots, prec):
     assert np.all(q[:, invariant_indices(K, L)] == 0.0)
 
 
+@pytest.mark.parametrize("K,L", [(4, 4), (12, 12), (16, 16)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_quadratic_homogeneity_bitwise(K, L, prec):
+    """Q(2c) = 4 Q(c) exactly: scaling by a power of two commutes with every rounding
+    of the path (including the BF16 hi/lo split), so any deviation is a kernel bug."""
+    core = gpu_core("vhs", K, L, 0.5)
+    c = synth.perturbed_maxwellian(K, L, 9, seed=31 + K)
+    say(f"[homogeneity] K={K} L={L} {prec}")
+    q1 = run(core, c, prec)
+    q2 = run(core, 2.0 * c, prec)
+    assert np.array_equal(q2, 4.0 * q1)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp64_naive", "fp32", "bf16x3"])
 def test_unit_maxwellian_is_exact_fixed_point(prec):
     K = L = 4

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 from scipy.special import factorial, roots_genlaguerre, roots_hermite, roots_legendre, eval_legendre
 
-from oracle import apply, basis, core, gaunt, weakform
+from oracle import apply, basis, core, gaunt, rk, weakform
 from oracle_cache import coo, core_raw, core_zeroed, golden
 
 B0 = 1.0 / (4 * math.pi)
@@ -217,6 +217,27 @@ def test_bkw_identity():
         rhs = 2 * math.pi * B0 / 3 * (1 - Kt) * dck
         assert np.abs(Q[:kmax + 1] - rhs).max() < 1e-10 * max(1.0, np.abs(rhs).max())
         assert np.abs(Q[kmax + 1:]).max() < 1e-14
+
+
+def test_rk_schemes_reach_bkw_at_their_order():
+    """The BKW coefficients c(K(t)), K(t) = 1 - (1 - K0) exp(-t/6), solve the truncated
+    system dc/dt = Q(c) exactly (Maxwell molecules, b0 = 1/(4 pi)), so the integration
+    error is the scheme's alone: halving dt divides it by 2^p for a scheme of order p."""
+    kmax, L = 6, 0
+    R = core_zeroed(kmax, L, 0.0)
+    T = coo(L)
+    K0, t_end = 0.6, 1.2
+    exact = _bkw_coeffs(1.0 - (1.0 - K0) * math.exp(-t_end / 6.0), kmax)
+    c0 = _bkw_coeffs(K0, kmax)
+    for scheme, order in (("euler", 1), ("heun", 2), ("ssp3", 3), ("rk4", 4)):
+        errs = []
+        for n in (6, 12):
+            c = rk.integrate(R, T, c0, kmax, t_end / n, n, scheme)
+            assert c[0] == c0[0] and c[1] == c0[1]          # mass and energy rows
+            errs.append(np.abs(c - exact).max())
+        ratio = errs[0] / errs[1]
+        assert 0.8 * 2 ** order < ratio < 1.25 * 2 ** order, (scheme, errs)
+    assert errs[1] < 1e-8                                   # rk4 at dt = 0.1
 
 
 # ---------------------------------------------------------------- hard spheres
