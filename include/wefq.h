@@ -107,6 +107,18 @@ wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count);
 wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* Q,
                          int64_t B, int64_t ld_f, int64_t ld_q, void* stream);
 
+/* Jacobian-vector product out = J(c) d = Q(c, d) + Q(d, c), the derivative of Q(f, f)
+ * at f = c in the direction d, where Q(f, g) = sum C_{a1 a2 a3} f_a2 g_a3 is the
+ * bilinear form of Section 2.3 (so J(c) c = 2 Q(c, c) and J(e_000) is the linearized
+ * operator).  c, d, out: device pointers, row-major [B][ld], ld >= N, double for
+ * WEFQ_FP64 and float for WEFQ_FP32 (the two precisions offered), aligned to the
+ * element size; c and d may alias each other but not out.  out is overwritten, its
+ * invariant rows are exactly 0.  Asynchronous on stream; allocates nothing.  Both
+ * inputs are staged in LDS, so the cell tile is at most half that of wefq_apply_Q;
+ * WEFQ_EUNSUPPORTED when two tiles of 4 cells do not fit (FP64 at Kmax = Lmax = 16). */
+wefq_status wefq_apply_J(wefq_handle h, int32_t precision, const void* c, const void* d, void* out, int64_t B,
+                         int64_t ld_c, int64_t ld_d, int64_t ld_out, void* stream);
+
 /* FP64 check of the five collision-invariant rows (Section 4.4) of a computed Q:
  * *max_abs = max over cells of |Q| on those rows (exactly 0 when conservation
  * holds; NaN if any of them is NaN).  Q as for wefq_apply_Q with the same precision.

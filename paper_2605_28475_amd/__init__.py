@@ -86,6 +86,28 @@ class Core:
                                            _stream_ptr(stream, f2.device)))
         return out[0] if squeeze else out
 
+    def apply_J(self, c, d, out=None, precision=None, stream=None):
+        """Jacobian-vector product J(c) d = Q(c, d) + Q(d, c) for [B, N] device tensors."""
+        import torch
+        squeeze = c.dim() == 1
+        c2 = c.unsqueeze(0) if squeeze else c
+        d2 = d.unsqueeze(0) if d.dim() == 1 else d
+        prec = self._prec(c2, precision)
+        want = torch.float64 if prec == FP64 else torch.float32
+        for t in (c2, d2):
+            if t.dtype != want or t.device.type != "cuda" or t.stride(-1) != 1:
+                raise ValueError(f"c and d must be CUDA {want} tensors with unit stride in the last dimension")
+        if d2.shape != c2.shape:
+            raise ValueError("c and d must have the same shape")
+        B = c2.shape[0]
+        if out is None:
+            out = torch.empty((B, c2.shape[1]), dtype=want, device=c2.device)
+        ld = lambda t: t.stride(0) if B > 1 else t.shape[1]
+        _lib.check(_lib.lib().wefq_apply_J(self._h, prec, ctypes.c_void_p(c2.data_ptr()),
+                                           ctypes.c_void_p(d2.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
+                                           ld(c2), ld(d2), ld(out), _stream_ptr(stream, c2.device)))
+        return out[0] if squeeze else out
+
     def check_conservation(self, Q, precision=None, stream=None):
         import torch
         Q2 = Q.unsqueeze(0) if Q.dim() == 1 else Q

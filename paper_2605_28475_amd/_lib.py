@@ -48,6 +48,9 @@ _SIGNATURES = [
     ("wefq_core_download_R", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     ("wefq_apply_Q", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]),
+    ("wefq_apply_J", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_void_p]),
     ("wefq_check_conservation", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                                ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     ("wefq_destroy", ctypes.c_int, [ctypes.c_void_p]),

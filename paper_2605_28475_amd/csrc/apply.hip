@@ -208,7 +208,7 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
                              int64_t ldf, int64_t ldq, hipStream_t s) {
   if (B == 0) return hipSuccess;
   MfmaParams p;
-  p.f = f; p.Q = Q; p.B = B; p.ldf = ldf; p.ldq = ldq;
+  p.f = f; p.g = nullptr; p.Q = Q; p.B = B; p.ldf = ldf; p.ldg = 0; p.ldq = ldq;
   p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
   p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
   p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.spair = h->d_spair; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
@@ -221,16 +221,7 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   if (slots == 0) return hipErrorInvalidValue;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
-  // Small batches: split each tile's work units over several workgroups, so that the
-  // launch still covers about two workgroups per compute unit (latency mode); every
-  // workgroup keeps at least 4 units for its 8 waves.
-  p.nsplit = 1;
-  const int64_t target = 2 * (int64_t)h->cu_count;
-  if (ntiles < target) {
-    const int64_t want = (target + ntiles - 1) / ntiles;
-    const int64_t cap = h->nunits / 4 > 1 ? h->nunits / 4 : 1;
-    p.nsplit = (int)(want < cap ? want : cap);
-  }
+  p.nsplit = tile_splits(h, ntiles);
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   switch (h->H) {
     case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);

@@ -18,8 +18,9 @@ __device__ inline bool invariant_row(int q1, int k1) {
 
 struct MfmaParams {
   const void* f;
+  const void* g;           // second input of the Jacobian-vector product (unused otherwise)
   void* Q;
-  int64_t B, ldf, ldq;
+  int64_t B, ldf, ldg, ldq;
   int NK, NQ, N;
   int nunits;
   int nsplit;              // workgroups sharing one cell tile; each takes every nsplit-th unit
@@ -51,6 +52,14 @@ template <> struct ModeTraits<0> { typedef float T; typedef v4f acc_t; };
 template <> struct ModeTraits<1> { typedef float T; typedef v4f acc_t; };
 template <> struct ModeTraits<2> { typedef double T; typedef v4d acc_t; };
 
+// The LDS rows one coupling step reads: the q2 row u and the q3 rows a (and b for a
+// pair) of the first input; with two inputs also the same rows of the second (g).
+template <typename T, int H, bool TWO>
+struct Rows {
+  T u[H], a[H], b[H];
+  T ug[TWO ? H : 1], ag[TWO ? H : 1], bg[TWO ? H : 1];
+};
+
 // Phi += u (x) w over an H x H quadrant.
 template <int H, typename T>
 __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
@@ -63,7 +72,7 @@ __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
 // One cell tile: stage f, then process the (l1, q1-group) work units split, split + nsplit, ...
 // (all of them when nsplit = 1).  Each output row belongs to one unit, so splitting a tile
 // over several workgroups changes neither the work per row nor its order.
-template <int H, int SLOTS, int RT, int MODE>
+template <int H, int SLOTS, int RT, int MODE, bool TWO = false>
 __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int split, unsigned char* lds_raw,
                                           int* unit_ctr_p) {
   typedef typename ModeTraits<MODE>::T T;
@@ -75,26 +84,34 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   constexpr int NP = GQ / SLOTS > 0 ? GQ / SLOTS : 1;
   T* fs = reinterpret_cast<T*>(lds_raw);
   int& unit_ctr = *unit_ctr_p;
-  const T* f = static_cast<const T*>(p.f);
   T* Qo = static_cast<T*>(p.Q);
   const int NK = p.NK;
   const int64_t cell0 = tile * TB;
   // stage the coefficient tile: fs[(q * NKp + k + pd * (k >= H)) * TB + cell], with the
   // zero pad and tail rows of the layout described with tile_upper_row
+  // (with two inputs the second tile follows the first, gofs elements later)
   const int pd = tile_pad_rows(NK, H, TB);
   const int NKp = NK + pd;
-  for (int idx = threadIdx.x; idx < TB * p.N; idx += blockDim.x) {
-    const int cl = idx / p.N, n = idx - cl * p.N;
-    const int q = n / NK, k = n - q * NK;
-    const int64_t cell = cell0 + cl;
-    fs[(q * NKp + k + (k >= H ? pd : 0)) * TB + cl] = (cell < p.B) ? f[cell * p.ldf + n] : T(0);
-  }
-  if (pd)
-    for (int idx = threadIdx.x; idx < TB * p.NQ; idx += blockDim.x) {
-      const int q = idx / TB, cl = idx - q * TB;
-      fs[(q * NKp + H) * TB + cl] = T(0);
+  const int tail = tile_tail_rows(NK, H);
+  const int gofs = TWO ? (p.NQ * NKp + tail) * TB : 0;
+#pragma unroll
+  for (int in = 0; in < (TWO ? 2 : 1); ++in) {
+    const T* src = static_cast<const T*>(in ? p.g : p.f);
+    const int64_t ld = in ? p.ldg : p.ldf;
+    T* dst = fs + in * gofs;
+    for (int idx = threadIdx.x; idx < TB * p.N; idx += blockDim.x) {
+      const int cl = idx / p.N, n = idx - cl * p.N;
+      const int q = n / NK, k = n - q * NK;
+      const int64_t cell = cell0 + cl;
+      dst[(q * NKp + k + (k >= H ? pd : 0)) * TB + cl] = (cell < p.B) ? src[cell * ld + n] : T(0);
     }
-  if (tile_tail_rows(NK, H) && threadIdx.x < TB) fs[p.NQ * NKp * TB + threadIdx.x] = T(0);
+    if (pd)
+      for (int idx = threadIdx.x; idx < TB * p.NQ; idx += blockDim.x) {
+        const int q = idx / TB, cl = idx - q * TB;
+        dst[(q * NKp + H) * TB + cl] = T(0);
+      }
+    if (tail && threadIdx.x < TB) dst[p.NQ * NKp * TB + threadIdx.x] = T(0);
+  }
   if (threadIdx.x == 0) unit_ctr = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -174,7 +191,53 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
         for (int t = 0; t < U * 8; ++t) phi[t] = T(0);
         // The slice's rows come as pairs sharing q2, then single rows.  A pair adds
         // f_{k2,q2} (g_a f_{k3,q3a} + g_b f_{k3,q3b}) to Phi: one outer product for
-        // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.
+        // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.  With two inputs c, d (the
+        // Jacobian-vector product) each product x (x) y becomes c_x (x) d_y + d_x (x) c_y.
+        auto weight = [&](int e) -> T { return MODE == 2 ? (T)mg64[e] : (T)mg[e]; };
+        auto gather = [&](uint32_t qa, uint32_t qb, Rows<T, H, TWO>& x, bool pair) {
+          const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
+          const T* pa = lane_w + (int)(qa >> 16) * TB;
+          const T* pb = lane_w + (int)(qb >> 16) * TB;
+#pragma unroll
+          for (int a = 0; a < H; ++a) {
+            x.u[a] = pu[a * TB];
+            x.a[a] = pa[a * TB];
+            if (pair) x.b[a] = pb[a * TB];
+            if constexpr (TWO) {
+              x.ug[a] = pu[gofs + a * TB];
+              x.ag[a] = pa[gofs + a * TB];
+              if (pair) x.bg[a] = pb[gofs + a * TB];
+            }
+          }
+        };
+        auto pair_acc = [&](T ga, T gb, const Rows<T, H, TWO>& x) {
+          T wf[H];
+#pragma unroll
+          for (int b = 0; b < H; ++b) wf[b] = fma(gb, x.b[b], ga * x.a[b]);
+          if constexpr (TWO) {
+            T wg[H];
+#pragma unroll
+            for (int b = 0; b < H; ++b) wg[b] = fma(gb, x.bg[b], ga * x.ag[b]);
+            outer_product<H>(phi, x.u, wg);
+            outer_product<H>(phi, x.ug, wf);
+          } else {
+            outer_product<H>(phi, x.u, wf);
+          }
+        };
+        auto single_acc = [&](T gg, const Rows<T, H, TWO>& x) {
+          T uu[H];
+#pragma unroll
+          for (int a = 0; a < H; ++a) uu[a] = gg * x.u[a];
+          if constexpr (TWO) {
+            T ug[H];
+#pragma unroll
+            for (int a = 0; a < H; ++a) ug[a] = gg * x.ug[a];
+            outer_product<H>(phi, uu, x.ag);
+            outer_product<H>(phi, ug, x.a);
+          } else {
+            outer_product<H>(phi, uu, x.a);
+          }
+        };
         if constexpr (SLOTS == 1) {     // the slice is shared by the whole wave
           const int s = soff + units[ub + 2 + gi];
           const int e0 = sptr[s], e1 = sptr[s + 1], ep = spair[s];
@@ -182,67 +245,29 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
           // while the outer product of the current one accumulates (the arrays
           // carry tail slack, whose row offsets point at LDS row 0)
           if (e0 < ep) {
-            uint32_t qa = mq[e0], qb = mq[e0 + 1];
-            T ga = MODE == 2 ? (T)mg64[e0] : (T)mg[e0];
-            T gb = MODE == 2 ? (T)mg64[e0 + 1] : (T)mg[e0 + 1];
-            T fu[H], fa[H], fb[H];
-            {
-              const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
-              const T* pa = lane_w + (int)(qa >> 16) * TB;
-              const T* pb = lane_w + (int)(qb >> 16) * TB;
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fa[a] = pa[a * TB]; fb[a] = pb[a * TB]; }
-            }
+            T ga = weight(e0), gb = weight(e0 + 1);
+            Rows<T, H, TWO> cur;
+            gather(mq[e0], mq[e0 + 1], cur, true);
             for (int e = e0; e < ep; e += 2) {
-              const uint32_t qna = mq[e + 2], qnb = mq[e + 3];
-              const T gna = MODE == 2 ? (T)mg64[e + 2] : (T)mg[e + 2];
-              const T gnb = MODE == 2 ? (T)mg64[e + 3] : (T)mg[e + 3];
-              const T* pu = lane_u + (int)(qna & 0xffffu) * TB;
-              const T* pa = lane_w + (int)(qna >> 16) * TB;
-              const T* pb = lane_w + (int)(qnb >> 16) * TB;
-              T nu[H], na[H], nb[H];
-#pragma unroll
-              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; na[a] = pa[a * TB]; nb[a] = pb[a * TB]; }
-              T ww[H];
-#pragma unroll
-              for (int b = 0; b < H; ++b) ww[b] = fma(gb, fb[b], ga * fa[b]);
-#pragma unroll
-              for (int a = 0; a < H; ++a)
-#pragma unroll
-                for (int b = 0; b < H; ++b) phi[a * H + b] = fma(fu[a], ww[b], phi[a * H + b]);
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fa[a] = na[a]; fb[a] = nb[a]; }
+              const T gna = weight(e + 2), gnb = weight(e + 3);
+              Rows<T, H, TWO> nxt;
+              gather(mq[e + 2], mq[e + 3], nxt, true);
+              pair_acc(ga, gb, cur);
+              cur = nxt;
               ga = gna;
               gb = gnb;
             }
           }
           if (ep < e1) {
-            uint32_t qq = mq[ep];
-            T gg = MODE == 2 ? (T)mg64[ep] : (T)mg[ep];
-            T fu[H], fw[H];
-            {
-              const T* pu = lane_u + (int)(qq & 0xffffu) * TB;     // q * NKp rows
-              const T* pw = lane_w + (int)(qq >> 16) * TB;
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fw[a] = pw[a * TB]; }
-            }
+            T gg = weight(ep);
+            Rows<T, H, TWO> cur;
+            gather(mq[ep], 0u, cur, false);
             for (int e = ep; e < e1; ++e) {
-              const uint32_t qn = mq[e + 1];
-              const T gn = MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1];
-              const T* pu = lane_u + (int)(qn & 0xffffu) * TB;
-              const T* pw = lane_w + (int)(qn >> 16) * TB;
-              T nu[H], nw[H];
-#pragma unroll
-              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; nw[a] = pw[a * TB]; }
-              T uu[H];
-#pragma unroll
-              for (int a = 0; a < H; ++a) uu[a] = gg * fu[a];
-#pragma unroll
-              for (int a = 0; a < H; ++a)
-#pragma unroll
-                for (int b = 0; b < H; ++b) phi[a * H + b] = fma(uu[a], fw[b], phi[a * H + b]);
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fw[a] = nw[a]; }
+              const T gn = weight(e + 1);
+              Rows<T, H, TWO> nxt;
+              gather(mq[e + 1], 0u, nxt, false);
+              single_acc(gg, cur);
+              cur = nxt;
               gg = gn;
             }
           }
@@ -275,8 +300,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
               if (i < ((sep[sl] - se0[sl]) >> 1)) {
                 const int e = se0[sl] + 2 * i;
                 const uint32_t xa = mq[e], xb = mq[e + 1];
-                const T ya = MODE == 2 ? (T)mg64[e] : (T)mg[e];
-                const T yb = MODE == 2 ? (T)mg64[e + 1] : (T)mg[e + 1];
+                const T ya = weight(e), yb = weight(e + 1);
                 if (slot == sl) { qa = xa; qb = xb; ga = ya; gb = yb; }
               }
             }
@@ -289,65 +313,43 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
               if (i < se1[sl] - sep[sl]) {
                 const int e = sep[sl] + i;
                 const uint32_t x = mq[e];
-                const T y = MODE == 2 ? (T)mg64[e] : (T)mg[e];
+                const T y = weight(e);
                 if (slot == sl) { qq = x; gg = y; }
               }
             }
           };
           if (maxp > 0) {
             uint32_t qa, qb;
-            T ga, gb, fu[H], fa[H], fb[H];
+            T ga, gb;
+            Rows<T, H, TWO> cur;
             fetch_pair(0, qa, qb, ga, gb);
-            {
-              const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
-              const T* pa = lane_w + (int)(qa >> 16) * TB;
-              const T* pb = lane_w + (int)(qb >> 16) * TB;
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fa[a] = pa[a * TB]; fb[a] = pb[a * TB]; }
-            }
+            gather(qa, qb, cur, true);
             for (int i = 0; i < maxp; ++i) {
               uint32_t qna, qnb;
-              T gna, gnb, nu[H], na[H], nb[H];
+              T gna, gnb;
+              Rows<T, H, TWO> nxt;
               fetch_pair(i + 1, qna, qnb, gna, gnb);
-              const T* pu = lane_u + (int)(qna & 0xffffu) * TB;
-              const T* pa = lane_w + (int)(qna >> 16) * TB;
-              const T* pb = lane_w + (int)(qnb >> 16) * TB;
-#pragma unroll
-              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; na[a] = pa[a * TB]; nb[a] = pb[a * TB]; }
-              T ww[H];
-#pragma unroll
-              for (int b = 0; b < H; ++b) ww[b] = fma(gb, fb[b], ga * fa[b]);
-              outer_product<H>(phi, fu, ww);
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fa[a] = na[a]; fb[a] = nb[a]; }
+              gather(qna, qnb, nxt, true);
+              pair_acc(ga, gb, cur);
+              cur = nxt;
               ga = gna;
               gb = gnb;
             }
           }
           if (maxs > 0) {
             uint32_t qq;
-            T gg, fu[H], fw[H];
+            T gg;
+            Rows<T, H, TWO> cur;
             fetch_single(0, qq, gg);
-            {
-              const T* pu = lane_u + (int)(qq & 0xffffu) * TB;
-              const T* pw = lane_w + (int)(qq >> 16) * TB;
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = pu[a * TB]; fw[a] = pw[a * TB]; }
-            }
+            gather(qq, 0u, cur, false);
             for (int i = 0; i < maxs; ++i) {
               uint32_t qn;
-              T gn, nu[H], nw[H];
+              T gn;
+              Rows<T, H, TWO> nxt;
               fetch_single(i + 1, qn, gn);
-              const T* pu = lane_u + (int)(qn & 0xffffu) * TB;
-              const T* pw = lane_w + (int)(qn >> 16) * TB;
-#pragma unroll
-              for (int a = 0; a < H; ++a) { nu[a] = pu[a * TB]; nw[a] = pw[a * TB]; }
-              T uu[H];
-#pragma unroll
-              for (int a = 0; a < H; ++a) uu[a] = gg * fu[a];
-              outer_product<H>(phi, uu, fw);
-#pragma unroll
-              for (int a = 0; a < H; ++a) { fu[a] = nu[a]; fw[a] = nw[a]; }
+              gather(qn, 0u, nxt, false);
+              single_acc(gg, cur);
+              cur = nxt;
               gg = gn;
             }
           }

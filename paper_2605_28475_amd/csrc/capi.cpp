@@ -444,6 +444,31 @@ wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* 
   return WEFQ_OK;
 }
 
+wefq_status wefq_apply_J(wefq_handle h, int32_t precision, const void* c, const void* d, void* out, int64_t B,
+                         int64_t ld_c, int64_t ld_d, int64_t ld_out, void* stream) {
+  if (h && precision != WEFQ_FP64 && precision != WEFQ_FP32)
+    return fail(WEFQ_EINVAL, "the Jacobian-vector product runs in FP64 or FP32");
+  wefq_status st = check_batch(h, precision, c, d, B, ld_c, ld_d);
+  if (st != WEFQ_OK || B == 0) return st;
+  if (!d || !out) return fail(WEFQ_EINVAL, "null direction or output pointer");
+  if (ld_out < h->N) return fail(WEFQ_EINVAL, "leading dimension smaller than N");
+  const size_t es = precision == WEFQ_FP64 ? 8 : 4;
+  if ((uintptr_t)out & (es - 1)) return fail(WEFQ_EINVAL, "pointers must be aligned to the element size");
+  const char* ob = (const char*)out;
+  const size_t on = (size_t)B * ld_out * es;
+  for (const void* in : {c, d}) {
+    const char* ib = (const char*)in;
+    const size_t inn = (size_t)B * (in == c ? ld_c : ld_d) * es;
+    if (ib < ob + on && ob < ib + inn) return fail(WEFQ_EINVAL, "the output must not overlap c or d");
+  }
+  if (2 * tile_lds_bytes(h, 4, es) > (size_t)h->lds_limit)
+    return fail(WEFQ_EUNSUPPORTED, "two coefficient tiles do not fit in LDS for this truncation");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+  hipError_t e = launch_apply_jvp(h, precision, c, d, out, B, ld_c, ld_d, ld_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return WEFQ_OK;
+}
+
 wefq_status wefq_check_conservation(wefq_handle h, int32_t precision, const void* Q, int64_t B, int64_t ld_q,
                                     double* max_abs, void* stream) {
   if (!max_abs) return fail(WEFQ_EINVAL, "null result pointer");

@@ -161,7 +161,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     SegDesc& d = descs[i];
     std::memset(&d, 0, sizeof(d));
     MfmaParams& p = d.p;
-    p.f = g.f; p.Q = g.Q; p.B = g.B; p.ldf = g.ld_f; p.ldq = g.ld_q;
+    p.f = g.f; p.g = nullptr; p.Q = g.Q; p.B = g.B; p.ldf = g.ld_f; p.ldg = 0; p.ldq = g.ld_q;
     p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
     p.nunits = h->nunits; p.nsplit = 1; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
     p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.spair = h->d_spair; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;

@@ -86,6 +86,18 @@ __host__ __device__ inline int tile_upper_row(int NK, int H, int TB) {
   return tile_upper_k(NK, H) + tile_pad_rows(NK, H, TB);
 }
 
+// Workgroups per cell tile for a launch of ntiles tiles: small batches split each tile's
+// work units over several workgroups, so that the launch still covers about two
+// workgroups per compute unit (latency mode); every workgroup keeps at least 4 units
+// for its 8 waves.
+inline int tile_splits(const wefq_core* h, int64_t ntiles) {
+  const int64_t target = 2 * (int64_t)h->cu_count;
+  if (ntiles <= 0 || ntiles >= target) return 1;
+  const int64_t want = (target + ntiles - 1) / ntiles;
+  const int64_t cap = h->nunits / 4 > 1 ? h->nunits / 4 : 1;
+  return (int)(want < cap ? want : cap);
+}
+
 // Kernel mode of a precision: 0 FP32, 1 BF16X3, 2 FP64 (tiled); -1 otherwise.
 inline int mfma_mode(int precision) {
   return precision == WEFQ_FP32 ? 0 : precision == WEFQ_BF16X3 ? 1 : precision == WEFQ_FP64 ? 2 : -1;
@@ -127,6 +139,9 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
 // Private (scratch) bytes per lane of the MFMA kernel instance of a tile shape:
 // nonzero when it spills registers.  Returns -1 for a shape with no instance.
 int mfma_spill_bytes(const wefq_core* h, int mode, int slots);
+// Jacobian-vector product out = J(c) d = Q(c, d) + Q(d, c) for FP32 or FP64 (jvp.hip).
+hipError_t launch_apply_jvp(const wefq_core* h, int precision, const void* c, const void* d, void* out,
+                            int64_t B, int64_t ldc, int64_t ldd, int64_t ldo, hipStream_t s);
 hipError_t launch_check(const wefq_core* h, int precision, const void* Q, int64_t B,
                         int64_t ldq, hipStream_t s);
 

@@ -219,6 +219,27 @@ def test_bkw_identity():
         assert np.abs(Q[kmax + 1:]).max() < 1e-14
 
 
+def test_bilinear_form_and_jacobian():
+    """Q(f, g) reduces to Q(f) on the diagonal, and the Jacobian-vector product obeys the
+    polarization identity Q(c + d) - Q(c) - Q(d) = J(c) d (exact for a quadratic form);
+    the collision tensor is not symmetric in its two inputs (the loss term), so the
+    bilinear form is not either."""
+    K, L = 3, 3
+    R = core_zeroed(K, L, 1.0)
+    T = coo(L)
+    rng = np.random.default_rng(3)
+    c = rng.standard_normal(basis.num_modes(K, L))
+    d = rng.standard_normal(basis.num_modes(K, L))
+    qc = apply.apply_q(R, T, c, K)
+    assert np.abs(apply.apply_bilinear(R, T, c, c, K) - qc).max() < 1e-13 * np.abs(qc).max()
+    j = apply.apply_jvp(R, T, c, d, K)
+    pol = apply.apply_q(R, T, c + d, K) - qc - apply.apply_q(R, T, d, K)
+    assert np.abs(j - pol).max() < 1e-12 * np.abs(j).max()
+    assert np.abs(apply.apply_jvp(R, T, c, c, K) - 2 * qc).max() < 1e-13 * np.abs(qc).max()
+    asym = apply.apply_bilinear(R, T, c, d, K) - apply.apply_bilinear(R, T, d, c, K)
+    assert np.abs(asym).max() > 1e-3 * np.abs(j).max()
+
+
 def test_rk_schemes_reach_bkw_at_their_order():
     """The BKW coefficients c(K(t)), K(t) = 1 - (1 - K0) exp(-t/6), solve the truncated
     system dc/dt = Q(c) exactly (Maxwell molecules, b0 = 1/(4 pi)), so the integration
