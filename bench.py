@@ -237,7 +237,7 @@ def bench_jvp(args, torch, wefq, synth):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     K, L, B, gamma = args.K, args.L, args.cells, args.gamma
-    core = wefq.Core("vhs", K, L, gamma=gamma, device=0, precisions=("fp64", "fp32"))
+    core = wefq.Core("vhs", K, L, gamma=gamma, device=0, precisions=("fp64", "fp32", "bilinear"))
     info = core.info
     NK = K + 1
     flop_cell = 2.0 * 2 * NK * NK * info["N_G"] + 2.0 * NK ** 3 * info["N_S"]
@@ -251,10 +251,11 @@ def bench_jvp(args, torch, wefq, synth):
         n = args.steps if prec == "fp32" else max(3, args.steps // 20)
         ms, _ = time_steps(lambda: core.apply_J(ct, dd, out=out, precision=prec), n, stream, torch)
         msq, _ = time_steps(lambda: core.apply_Q(ct, out=out, precision=prec), max(3, n // 4), stream, torch)
+        msb, _ = time_steps(lambda: core.apply_Qfg(ct, dd, out=out, precision=prec), max(3, n // 4), stream, torch)
         t = float(np.mean(ms)) * 1e-3
         res[prec] = {"cells_per_s": B / t, "kernel_ms": 1e3 * t, "p50_ms": float(np.percentile(ms, 50)),
                      "p99_ms": float(np.percentile(ms, 99)), "apply_Q_ms": float(np.mean(msq)),
-                     "tflops": flop_cell * B / t / 1e12}
+                     "bilinear_Qfg_ms": float(np.mean(msb)), "tflops": flop_cell * B / t / 1e12}
         del ct, dd, out
     t32 = res["fp32"]["kernel_ms"] * 1e-3
     out = {"metric": "J(c) d cell-evals/sec at Kmax=Lmax=12", "value": B / t32, "unit": "cells/s", "n_gpus": 1,

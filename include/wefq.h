@@ -53,9 +53,12 @@ typedef enum {
   WEFQ_FP32 = 2,          /* FP32 angular coupling + FP32 MFMA radial contraction; float */
   WEFQ_BF16X3 = 4,        /* FP32 angular coupling + split hi/lo BF16 MFMA (3 products,
                              FP32 accumulation); f and Q are float */
-  WEFQ_FP64_NAIVE = 8     /* the paper's naive ordering of the factorized sum (Section 4.5.2):
+  WEFQ_FP64_NAIVE = 8,    /* the paper's naive ordering of the factorized sum (Section 4.5.2):
                              every COO row contracts its full K^3 block, FP64, one thread per
                              output; a reference ordering, memory-bound on R; double */
+  WEFQ_PREP_BILINEAR = 16 /* not a precision: in wefq_core_desc.precisions, also prepare the
+                             tables of the non-symmetric bilinear form (wefq_apply_Qfg) for the
+                             FP64 / FP32 precisions requested */
 } wefq_precision;
 
 /* Descriptor of a radial core.  The collision kernel is B(u, cos chi) = b0 u^gamma
@@ -118,6 +121,17 @@ wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* 
  * WEFQ_EUNSUPPORTED when two tiles of 4 cells do not fit (FP64 at Kmax = Lmax = 16). */
 wefq_status wefq_apply_J(wefq_handle h, int32_t precision, const void* c, const void* d, void* out, int64_t B,
                          int64_t ld_c, int64_t ld_d, int64_t ld_out, void* stream);
+
+/* The bilinear form itself: out = Q(f, g) = sum C_{a1 a2 a3} f_a2 g_a3 (Section 2.3; f is
+ * the particle whose distribution the loss term depletes, g its collision partner), so
+ * Q(f, f) is wefq_apply_Q and Q(f, g) + Q(g, f) = wefq_apply_J.  Arguments as for
+ * wefq_apply_J; the core must have been built with WEFQ_PREP_BILINEAR in its precisions
+ * (otherwise EINVAL).  Two launches on stream: the symmetric part, then the antisymmetric
+ * part added into out.  The mass row of out is exactly 0; the momentum and energy rows are
+ * not zero in general (only Q(f, g) + Q(g, f) conserves them), and they come from the core
+ * before the invariant-row zeroing of Section 4.4. */
+wefq_status wefq_apply_Qfg(wefq_handle h, int32_t precision, const void* f, const void* g, void* out, int64_t B,
+                           int64_t ld_f, int64_t ld_g, int64_t ld_out, void* stream);
 
 /* FP64 check of the five collision-invariant rows (Section 4.4) of a computed Q:
  * *max_abs = max over cells of |Q| on those rows (exactly 0 when conservation

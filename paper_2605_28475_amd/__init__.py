@@ -14,7 +14,8 @@ from ._lib import (BF16X3, FP32, FP64, FP64_NAIVE, HARD_SPHERE, MAXWELL, RK_CLAS
                    RK_SSP3, VHS, WefqError)
 
 MODELS = {"maxwell": MAXWELL, "mm": MAXWELL, "hard_sphere": HARD_SPHERE, "hs": HARD_SPHERE, "vhs": VHS}
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp64_naive": FP64_NAIVE}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp64_naive": FP64_NAIVE,
+              "bilinear": _lib.PREP_BILINEAR}
 RK_SCHEMES = {"euler": RK_EULER, "heun": RK_HEUN, "ssp3": RK_SSP3, "rk4": RK_CLASSIC4}
 
 
@@ -88,6 +89,13 @@ class Core:
 
     def apply_J(self, c, d, out=None, precision=None, stream=None):
         """Jacobian-vector product J(c) d = Q(c, d) + Q(d, c) for [B, N] device tensors."""
+        return self._two_input("wefq_apply_J", c, d, out, precision, stream)
+
+    def apply_Qfg(self, f, g, out=None, precision=None, stream=None):
+        """Bilinear form Q(f, g) for [B, N] device tensors (core built with "bilinear")."""
+        return self._two_input("wefq_apply_Qfg", f, g, out, precision, stream)
+
+    def _two_input(self, fn, c, d, out, precision, stream):
         import torch
         squeeze = c.dim() == 1
         c2 = c.unsqueeze(0) if squeeze else c
@@ -103,7 +111,7 @@ class Core:
         if out is None:
             out = torch.empty((B, c2.shape[1]), dtype=want, device=c2.device)
         ld = lambda t: t.stride(0) if B > 1 else t.shape[1]
-        _lib.check(_lib.lib().wefq_apply_J(self._h, prec, ctypes.c_void_p(c2.data_ptr()),
+        _lib.check(getattr(_lib.lib(), fn)(self._h, prec, ctypes.c_void_p(c2.data_ptr()),
                                            ctypes.c_void_p(d2.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
                                            ld(c2), ld(d2), ld(out), _stream_ptr(stream, c2.device)))
         return out[0] if squeeze else out

@@ -6,7 +6,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwefq.so"
 
 WEFQ_OK, WEFQ_EINVAL, WEFQ_ENOMEM, WEFQ_EHIP, WEFQ_EUNSUPPORTED, WEFQ_EBUDGET = range(6)
 MAXWELL, HARD_SPHERE, VHS = 0, 1, 2
-FP64, FP32, BF16X3, FP64_NAIVE = 1, 2, 4, 8
+FP64, FP32, BF16X3, FP64_NAIVE, PREP_BILINEAR = 1, 2, 4, 8, 16
 RK_EULER, RK_HEUN, RK_SSP3, RK_CLASSIC4 = 1, 2, 3, 4
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED", 5: "EBUDGET"}
@@ -51,6 +51,9 @@ _SIGNATURES = [
     ("wefq_apply_J", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_void_p]),
+    ("wefq_apply_Qfg", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_void_p]),
     ("wefq_check_conservation", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                                ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     ("wefq_destroy", ctypes.c_int, [ctypes.c_void_p]),

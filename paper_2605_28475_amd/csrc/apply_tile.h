@@ -60,19 +60,22 @@ struct Rows {
   T ug[TWO ? H : 1], ag[TWO ? H : 1], bg[TWO ? H : 1];
 };
 
-// Phi += u (x) w over an H x H quadrant.
-template <int H, typename T>
+// Phi += u (x) w (or Phi -= u (x) w) over an H x H quadrant.
+template <int H, bool NEG = false, typename T>
 __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
 #pragma unroll
   for (int a = 0; a < H; ++a)
 #pragma unroll
-    for (int b = 0; b < H; ++b) phi[a * H + b] = fma(u[a], w[b], phi[a * H + b]);
+    for (int b = 0; b < H; ++b) phi[a * H + b] = fma(NEG ? -u[a] : u[a], w[b], phi[a * H + b]);
 }
 
 // One cell tile: stage f, then process the (l1, q1-group) work units split, split + nsplit, ...
 // (all of them when nsplit = 1).  Each output row belongs to one unit, so splitting a tile
 // over several workgroups changes neither the work per row nor its order.
-template <int H, int SLOTS, int RT, int MODE, bool TWO = false>
+// TWO: two inputs f, g; the coupling is symmetric, sum w (f_x (x) g_y + g_x (x) f_y), or with
+// ANTI antisymmetric, sum w (f_x (x) g_y - g_x (x) f_y), contracted with the tiles the caller
+// passes as the A operand, and the result combined as out = (out + result) / 2.
+template <int H, int SLOTS, int RT, int MODE, bool TWO = false, bool ANTI = false>
 __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int split, unsigned char* lds_raw,
                                           int* unit_ctr_p) {
   typedef typename ModeTraits<MODE>::T T;
@@ -219,7 +222,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
 #pragma unroll
             for (int b = 0; b < H; ++b) wg[b] = fma(gb, x.bg[b], ga * x.ag[b]);
             outer_product<H>(phi, x.u, wg);
-            outer_product<H>(phi, x.ug, wf);
+            outer_product<H, ANTI>(phi, x.ug, wf);
           } else {
             outer_product<H>(phi, x.u, wf);
           }
@@ -233,7 +236,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
 #pragma unroll
             for (int a = 0; a < H; ++a) ug[a] = gg * x.ug[a];
             outer_product<H>(phi, uu, x.ag);
-            outer_product<H>(phi, ug, x.a);
+            outer_product<H, ANTI>(phi, ug, x.a);
           } else {
             outer_product<H>(phi, uu, x.a);
           }
@@ -443,9 +446,14 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int k1 = MODE == 2 ? r + 4 * i : 4 * r + i;
-        if (k1 < NK) dst[k1] = invariant_row(q1, k1) ? T(0) : (T)acc[gi][i];
+        if (k1 < NK) {
+          T v = (T)acc[gi][i];
+          // the antisymmetric part keeps its momentum and energy rows; mass is zero for both
+          if constexpr (ANTI) dst[k1] = (q1 == 0 && k1 == 0) ? T(0) : T(0.5) * (dst[k1] + v);
+          else dst[k1] = invariant_row(q1, k1) ? T(0) : v;
+        }
       }
-      if (RT == 2 && r == 0) dst[16] = acc16[gi];
+      if (RT == 2 && r == 0) dst[16] = ANTI ? T(0.5) * (dst[16] + acc16[gi]) : acc16[gi];
     }
   }
 }

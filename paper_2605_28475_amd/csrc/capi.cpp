@@ -106,6 +106,31 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
               ch.l2 < ch.l3 ? Ra[((size_t)k1 * NK + k2) * NK + k3] + Rb[((size_t)k1 * NK + k3) * NK + k2]
                             : sc * (Ra[((size_t)k1 * NK + k2) * NK + k3] + Ra[((size_t)k1 * NK + k3) * NK + k2]);
   }
+  // Antisymmetric partner of the merged core, for the bilinear form Q(f, g):
+  // D = R^{(l1l2l3)}_{k1k2k3} - R^{(l1l3l2)}_{k1k3k2} (l2 < l3), (R_{k1k2k3} - R_{k1k3k2}) / 2 (l2 = l3),
+  // so that Q(f, g) = (R~ Phi_S + D Phi_A) / 2 with Phi_S, Phi_A the symmetric and
+  // antisymmetric two-input couplings.
+  // D is built from the core before the invariant-row zeroing, except the mass row
+  // (exactly zero for every pair of inputs); its momentum and energy rows carry the
+  // part of Q(f, g) that is antisymmetric in f and g.
+  const bool wantD = (h->precisions & WEFQ_PREP_BILINEAR) != 0;
+  std::vector<double> Dm;
+  if (wantD) {
+    Dm.resize((size_t)NTm * blk);
+    for (int m = 0; m < NTm; ++m) {
+      const Channel& ch = h->chans[mchan[m]];
+      const double* Ra = h->R64raw.data() + (size_t)mchan[m] * blk;
+      const double* Rb = ch.l2 < ch.l3 ? h->R64raw.data() + (size_t)cidx[(ch.l1 * (L + 1) + ch.l3) * (L + 1) + ch.l2] * blk : Ra;
+      const double sc = ch.l2 < ch.l3 ? 1.0 : 0.5;
+      for (int k1 = 0; k1 < NK; ++k1)
+        for (int k2 = 0; k2 < NK; ++k2)
+          for (int k3 = 0; k3 < NK; ++k3)
+            Dm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3] =
+                (ch.l1 == 0 && k1 == 0) ? 0.0 : sc * (Ra[((size_t)k1 * NK + k2) * NK + k3] - Rb[((size_t)k1 * NK + k3) * NK + k2]);
+    }
+    h->R64raw.clear();
+    h->R64raw.shrink_to_fit();
+  }
   std::vector<int> chan_begin(L + 2, 0);
   for (int m = 0; m < NTm; ++m) chan_begin[h->chans[mchan[m]].l1 + 1]++;
   for (int l = 0; l <= L; ++l) chan_begin[l + 1] += chan_begin[l];
@@ -214,7 +239,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   // (lower half) or k = tile_upper_k (upper half); upper-half rows outside [H, NK), the
   // one shared with the lower half or the one past the end, have zero weight.
   const int uk = tile_upper_k(NK, H);
-  auto Rval = [&](int m, int k1, int t, int r) -> double {
+  auto Tval = [&](const std::vector<double>& M, int m, int k1, int t, int r) -> double {
     if (t >= HH || k1 >= NK) return 0.0;
     int a = t / H, b = t % H;
     int h2 = r >> 1, h3 = r & 1;
@@ -222,8 +247,9 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     if (k2 >= NK || k3 >= NK) return 0.0;
     if (h2 && k2 < H) return 0.0;
     if (h3 && k3 < H) return 0.0;
-    return Rm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3];
+    return M[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3];
   };
+  auto Rval = [&](int m, int k1, int t, int r) -> double { return Tval(Rm, m, k1, t, r); };
   bool want32 = h->precisions & WEFQ_FP32, want16 = h->precisions & WEFQ_BF16X3, want64 = h->precisions & WEFQ_FP64;
   if ((want32 && h->slots[0] == 0) || (want16 && h->slots[1] == 0) || (want64 && h->slots[2] == 0)) {
     set_error("coefficient tile does not fit in LDS for this truncation");
@@ -257,6 +283,25 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
         for (int ln = 0; ln < 64; ++ln)
           t32[((size_t)m * HH + t) * 64 + ln] = (float)Rval(m, ln & 15, t, ln >> 4);
     if (!upload(h, h->d_Rt32, t32, s)) return false;
+  }
+  if (wantD) {                // the antisymmetric tiles in the same layouts (FP64 and FP32)
+    std::vector<double> d16;
+    if (RT == 2) {
+      d16.assign((size_t)NTm * 4 * HH, 0.0);
+      for (int m = 0; m < NTm; ++m)
+        for (int r = 0; r < 4; ++r)
+          for (int t = 0; t < HH; ++t) d16[((size_t)m * 4 + r) * HH + t] = Tval(Dm, m, 16, t, r);
+    }
+    std::vector<double> t64((size_t)NTm * HH * 64);
+    for (int m = 0; m < NTm; ++m)
+      for (int t = 0; t < HH; ++t)
+        for (int ln = 0; ln < 64; ++ln) t64[((size_t)m * HH + t) * 64 + ln] = Tval(Dm, m, ln & 15, t, ln >> 4);
+    std::vector<float> t32(t64.begin(), t64.end());
+    if ((want64 && !upload(h, h->d_Dt64, t64, s)) || (want32 && !upload(h, h->d_Dt32, t32, s))) return false;
+    if (RT == 2) {
+      std::vector<float> d16f(d16.begin(), d16.end());
+      if ((want64 && !upload(h, h->d_D16_64, d16, s)) || (want32 && !upload(h, h->d_D16_32, d16f, s))) return false;
+    }
   }
   if (want16) {
     std::vector<uint16_t> hi((size_t)NTm * UU * 64 * 8), lo(hi.size());
@@ -351,7 +396,7 @@ wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handl
     }
     if (!(gamma >= 0.0 && gamma <= 2.0)) return fail(WEFQ_EINVAL, "gamma must lie in [0, 2]");
     unsigned prec = desc->precisions ? desc->precisions : (WEFQ_FP64 | WEFQ_FP32 | WEFQ_BF16X3);
-    if (prec & ~15u) return fail(WEFQ_EINVAL, "unknown precision bits");
+    if (prec & ~31u) return fail(WEFQ_EINVAL, "unknown precision bits");
     if (prec & WEFQ_FP64_NAIVE) prec |= WEFQ_FP64;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(WEFQ_EHIP, "no HIP device available");
@@ -377,6 +422,9 @@ wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handl
     }
     hipStream_t s = (hipStream_t)stream;
     if (!build_radial_core(h, coo, s)) { free_core(h); return WEFQ_EHIP; }
+    // the bilinear form keeps the momentum and energy rows that the zeroing removes
+    // (they are antisymmetric in the two inputs, so they vanish for Q(f, f) only)
+    if (prec & WEFQ_PREP_BILINEAR) h->R64raw = h->R64;
     zero_invariants(h);
     if (!prepare_apply_tables(h, coo, s)) { free_core(h); return WEFQ_ENOMEM; }
     *out = h;
@@ -444,10 +492,11 @@ wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* 
   return WEFQ_OK;
 }
 
-wefq_status wefq_apply_J(wefq_handle h, int32_t precision, const void* c, const void* d, void* out, int64_t B,
-                         int64_t ld_c, int64_t ld_d, int64_t ld_out, void* stream) {
+// Validation shared by the two-input entry points.
+static wefq_status check_two(wefq_handle h, int32_t precision, const void* c, const void* d, void* out, int64_t B,
+                             int64_t ld_c, int64_t ld_d, int64_t ld_out) {
   if (h && precision != WEFQ_FP64 && precision != WEFQ_FP32)
-    return fail(WEFQ_EINVAL, "the Jacobian-vector product runs in FP64 or FP32");
+    return fail(WEFQ_EINVAL, "the two-input forms run in FP64 or FP32");
   wefq_status st = check_batch(h, precision, c, d, B, ld_c, ld_d);
   if (st != WEFQ_OK || B == 0) return st;
   if (!d || !out) return fail(WEFQ_EINVAL, "null direction or output pointer");
@@ -463,8 +512,27 @@ wefq_status wefq_apply_J(wefq_handle h, int32_t precision, const void* c, const 
   }
   if (2 * tile_lds_bytes(h, 4, es) > (size_t)h->lds_limit)
     return fail(WEFQ_EUNSUPPORTED, "two coefficient tiles do not fit in LDS for this truncation");
+  return WEFQ_OK;
+}
+
+wefq_status wefq_apply_J(wefq_handle h, int32_t precision, const void* c, const void* d, void* out, int64_t B,
+                         int64_t ld_c, int64_t ld_d, int64_t ld_out, void* stream) {
+  wefq_status st = check_two(h, precision, c, d, out, B, ld_c, ld_d, ld_out);
+  if (st != WEFQ_OK || B == 0) return st;
   if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
   hipError_t e = launch_apply_jvp(h, precision, c, d, out, B, ld_c, ld_d, ld_out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return WEFQ_OK;
+}
+
+wefq_status wefq_apply_Qfg(wefq_handle h, int32_t precision, const void* f, const void* g, void* out, int64_t B,
+                           int64_t ld_f, int64_t ld_g, int64_t ld_out, void* stream) {
+  wefq_status st = check_two(h, precision, f, g, out, B, ld_f, ld_g, ld_out);
+  if (st != WEFQ_OK || B == 0) return st;
+  if (!(h->precisions & WEFQ_PREP_BILINEAR))
+    return fail(WEFQ_EINVAL, "the bilinear-form tables were not prepared (WEFQ_PREP_BILINEAR)");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+  hipError_t e = launch_apply_qfg(h, precision, f, g, out, B, ld_f, ld_g, ld_out, (hipStream_t)stream);
   if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return WEFQ_OK;
 }

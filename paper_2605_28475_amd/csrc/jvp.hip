@@ -1,9 +1,12 @@
-// Jacobian-vector product of the collision operator: out = J(c) d = Q(c, d) + Q(d, c),
+// Two-input forms of the collision operator.  The Jacobian-vector product
+// out = J(c) d = Q(c, d) + Q(d, c),
 // the derivative of Q at c in the direction d (with Q(f, g) the bilinear form whose
 // diagonal is Q(f, f), Section 2.3).  It is the apply kernel with two inputs: per
 // slice the coupling accumulates sum_z g_z (c_{k2,q2z} d_{k3,q3z} + d_{k2,q2z} c_{k3,q3z}),
-// which the merged radial tiles contract exactly as they do f (x) f.  Both cell tiles
-// sit in LDS, so the default tile holds at most half as many cells as for Q(f, f).
+// which the merged radial tiles contract exactly as they do f (x) f.  The bilinear form
+// Q(f, g) itself adds the antisymmetric part: the coupling sum_z g_z (f_x (x) g_y -
+// g_x (x) f_y) contracted with the partner tiles D of the merged channels.  Both cell
+// tiles sit in LDS, so the default tile holds at most half as many cells as for Q(f, f).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -14,16 +17,16 @@
 
 namespace wefq {
 
-template <int H, int SLOTS, int RT, int MODE>
+template <int H, int SLOTS, int RT, int MODE, bool ANTI>
 __global__ __launch_bounds__(512) void apply_jvp_kernel(MfmaParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int unit_ctr;
-  mfma_tile<H, SLOTS, RT, MODE, true>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw, &unit_ctr);
+  mfma_tile<H, SLOTS, RT, MODE, true, ANTI>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw, &unit_ctr);
 }
 
 template <int H, int SLOTS, int RT, int MODE>
-static hipError_t launch_jvp_t(const MfmaParams& p, int64_t ntiles, size_t lds, hipStream_t s) {
-  auto k = apply_jvp_kernel<H, SLOTS, RT, MODE>;
+static hipError_t launch_jvp_t(const MfmaParams& p, bool anti, int64_t ntiles, size_t lds, hipStream_t s) {
+  auto k = anti ? apply_jvp_kernel<H, SLOTS, RT, MODE, true> : apply_jvp_kernel<H, SLOTS, RT, MODE, false>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3((unsigned)ntiles, (unsigned)p.nsplit), dim3(512), lds, s, p);
@@ -31,32 +34,35 @@ static hipError_t launch_jvp_t(const MfmaParams& p, int64_t ntiles, size_t lds, 
 }
 
 template <int H, int RT, int MODE>
-static hipError_t launch_jvp_s(const MfmaParams& p, int slots, int64_t ntiles, size_t lds, hipStream_t s) {
+static hipError_t launch_jvp_s(const MfmaParams& p, bool anti, int slots, int64_t ntiles, size_t lds,
+                               hipStream_t s) {
   switch (slots) {
-    case 1: return launch_jvp_t<H, 1, RT, MODE>(p, ntiles, lds, s);
-    case 2: return launch_jvp_t<H, 2, RT, MODE>(p, ntiles, lds, s);
-    case 4: return launch_jvp_t<H, 4, RT, MODE>(p, ntiles, lds, s);
+    case 1: return launch_jvp_t<H, 1, RT, MODE>(p, anti, ntiles, lds, s);
+    case 2: return launch_jvp_t<H, 2, RT, MODE>(p, anti, ntiles, lds, s);
+    case 4: return launch_jvp_t<H, 4, RT, MODE>(p, anti, ntiles, lds, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int H>
-static hipError_t launch_jvp_h(const MfmaParams& p, int mode, int slots, int rt, int64_t ntiles, size_t lds,
-                               hipStream_t s) {
+static hipError_t launch_jvp_h(const MfmaParams& p, bool anti, int mode, int slots, int rt, int64_t ntiles,
+                               size_t lds, hipStream_t s) {
   if (rt == 2) {
     if constexpr (H >= 8) {
-      if (mode == 0) return launch_jvp_s<H, 2, 0>(p, slots, ntiles, lds, s);
-      if (mode == 2) return launch_jvp_s<H, 2, 2>(p, slots, ntiles, lds, s);
+      if (mode == 0) return launch_jvp_s<H, 2, 0>(p, anti, slots, ntiles, lds, s);
+      if (mode == 2) return launch_jvp_s<H, 2, 2>(p, anti, slots, ntiles, lds, s);
     }
     return hipErrorInvalidValue;
   }
-  if (mode == 0) return launch_jvp_s<H, 1, 0>(p, slots, ntiles, lds, s);
-  if (mode == 2) return launch_jvp_s<H, 1, 2>(p, slots, ntiles, lds, s);
+  if (mode == 0) return launch_jvp_s<H, 1, 0>(p, anti, slots, ntiles, lds, s);
+  if (mode == 2) return launch_jvp_s<H, 1, 2>(p, anti, slots, ntiles, lds, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_apply_jvp(const wefq_core* h, int precision, const void* c, const void* d, void* out,
-                            int64_t B, int64_t ldc, int64_t ldd, int64_t ldo, hipStream_t s) {
+// One two-input launch: symmetric coupling with the merged tiles (anti = false), or the
+// antisymmetric coupling with the partner tiles, combined into out (anti = true).
+static hipError_t launch_two(const wefq_core* h, bool anti, int precision, const void* f, const void* g, void* out,
+                             int64_t B, int64_t ldf, int64_t ldg, int64_t ldo, hipStream_t s) {
   if (B == 0) return hipSuccess;
   const int mode = mfma_mode(precision);
   if (mode != 0 && mode != 2) return hipErrorInvalidValue;
@@ -66,29 +72,44 @@ hipError_t launch_apply_jvp(const wefq_core* h, int precision, const void* c, co
     if (2 * tile_lds_bytes(h, sl, elem) <= (size_t)h->lds_limit) { slots = sl; break; }
   if (slots == 0) return hipErrorInvalidValue;
   MfmaParams p;
-  p.f = c; p.g = d; p.Q = out; p.B = B; p.ldf = ldc; p.ldg = ldd; p.ldq = ldo;
+  p.f = f; p.g = g; p.Q = out; p.B = B; p.ldf = ldf; p.ldg = ldg; p.ldq = ldo;
   p.NK = h->NK; p.NQ = h->NQ; p.N = h->N;
   p.nunits = h->nunits; p.units = h->d_units; p.chan_begin = h->d_chan_begin;
   p.slice_off = h->d_slice_off; p.sptr = h->d_sptr; p.spair = h->d_spair; p.mq = h->d_mq; p.mq_pad = h->d_mq_pad;
   p.mg = h->d_mg; p.mg64 = h->d_mg64;
-  p.Rt32 = h->d_Rt32; p.Rt64 = h->d_Rt64; p.Rhi = h->d_Rhi; p.Rlo = h->d_Rlo;
-  p.R16_32 = h->d_R16_32; p.R16_64 = h->d_R16_64;
+  p.Rt32 = anti ? h->d_Dt32 : h->d_Rt32; p.Rt64 = anti ? h->d_Dt64 : h->d_Rt64;
+  p.R16_32 = anti ? h->d_D16_32 : h->d_R16_32; p.R16_64 = anti ? h->d_D16_64 : h->d_R16_64;
+  p.Rhi = nullptr; p.Rlo = nullptr;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
   p.nsplit = tile_splits(h, ntiles);
   const size_t lds = 2 * tile_lds_bytes(h, slots, elem);
   switch (h->H) {
-    case 1: return launch_jvp_h<1>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 2: return launch_jvp_h<2>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 3: return launch_jvp_h<3>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 4: return launch_jvp_h<4>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 5: return launch_jvp_h<5>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 6: return launch_jvp_h<6>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 7: return launch_jvp_h<7>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 8: return launch_jvp_h<8>(p, mode, slots, h->RT, ntiles, lds, s);
-    case 9: return launch_jvp_h<9>(p, mode, slots, h->RT, ntiles, lds, s);
+    case 1: return launch_jvp_h<1>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 2: return launch_jvp_h<2>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 3: return launch_jvp_h<3>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 4: return launch_jvp_h<4>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 5: return launch_jvp_h<5>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 6: return launch_jvp_h<6>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 7: return launch_jvp_h<7>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 8: return launch_jvp_h<8>(p, anti, mode, slots, h->RT, ntiles, lds, s);
+    case 9: return launch_jvp_h<9>(p, anti, mode, slots, h->RT, ntiles, lds, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_apply_jvp(const wefq_core* h, int precision, const void* c, const void* d, void* out,
+                            int64_t B, int64_t ldc, int64_t ldd, int64_t ldo, hipStream_t s) {
+  return launch_two(h, false, precision, c, d, out, B, ldc, ldd, ldo, s);
+}
+
+// Q(f, g) = (R~ Phi_S + D Phi_A) / 2: the symmetric launch writes R~ Phi_S = J(f) g, the
+// antisymmetric one adds D Phi_A and halves, on the same stream.
+hipError_t launch_apply_qfg(const wefq_core* h, int precision, const void* f, const void* g, void* out,
+                            int64_t B, int64_t ldf, int64_t ldg, int64_t ldo, hipStream_t s) {
+  hipError_t e = launch_two(h, false, precision, f, g, out, B, ldf, ldg, ldo, s);
+  if (e != hipSuccess) return e;
+  return launch_two(h, true, precision, f, g, out, B, ldf, ldg, ldo, s);
 }
 
 }  // namespace wefq

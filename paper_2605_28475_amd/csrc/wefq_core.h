@@ -20,6 +20,7 @@ struct wefq_core {
   int64_t device_bytes = 0;
   std::vector<wefq::Channel> chans;
   std::vector<double> R64;             // host copy, zeroed, [c][k1][k2][k3]
+  std::vector<double> R64raw;          // before the zeroing (bilinear-form tables only; freed after use)
 
   // FP64 plain path: COO rows grouped by q1 (CSR), paper channel ids
   double* dR64 = nullptr;
@@ -44,6 +45,10 @@ struct wefq_core {
   double* d_Rt64 = nullptr;            // [NTm][H*H][64]
   float* d_R16_32 = nullptr;           // NK = 17: row k1 = 16, [NTm][4][H*H]
   double* d_R16_64 = nullptr;
+  float* d_Dt32 = nullptr;             // antisymmetric partner tiles (bilinear form), layout of d_Rt32
+  double* d_Dt64 = nullptr;
+  float* d_D16_32 = nullptr;
+  double* d_D16_64 = nullptr;
   uint16_t* d_Rhi = nullptr;           // [NTm][ceil(H*H/8)][64][8] bf16 bits
   uint16_t* d_Rlo = nullptr;
   int* d_units = nullptr;              // [nunits][UNIT_STRIDE]: l1, count, q1 values
@@ -142,6 +147,9 @@ int mfma_spill_bytes(const wefq_core* h, int mode, int slots);
 // Jacobian-vector product out = J(c) d = Q(c, d) + Q(d, c) for FP32 or FP64 (jvp.hip).
 hipError_t launch_apply_jvp(const wefq_core* h, int precision, const void* c, const void* d, void* out,
                             int64_t B, int64_t ldc, int64_t ldd, int64_t ldo, hipStream_t s);
+// Bilinear form out = Q(f, g) for FP32 or FP64 (jvp.hip; needs the WEFQ_PREP_BILINEAR tables).
+hipError_t launch_apply_qfg(const wefq_core* h, int precision, const void* f, const void* g, void* out,
+                            int64_t B, int64_t ldf, int64_t ldg, int64_t ldo, hipStream_t s);
 hipError_t launch_check(const wefq_core* h, int precision, const void* Q, int64_t B,
                         int64_t ldq, hipStream_t s);
 

@@ -1,4 +1,5 @@
-"""Jacobian-vector product J(c) d = Q(c, d) + Q(d, c) on the GPU (wefq_apply_J) against the oracle."""
+"""Two-input forms on the GPU against the oracle: the Jacobian-vector product
+J(c) d = Q(c, d) + Q(d, c) (wefq_apply_J) and the bilinear form Q(f, g) (wefq_apply_Qfg)."""
 import ctypes
 
 import numpy as np
@@ -6,7 +7,7 @@ import pytest
 
 from gpu_common import dev, invariant_indices, rel_err, say, torch
 from oracle import apply as oapply
-from oracle_cache import coo, core_zeroed
+from oracle_cache import coo, core_raw, core_zeroed
 
 import paper_2605_28475_amd as wefq
 from paper_2605_28475_amd import _lib, synth
@@ -21,7 +22,7 @@ def gpu_core(model, K, L, gamma):
     key = (model, K, L, gamma)
     if key not in _cores:
         say(f"[build] {key}")
-        _cores[key] = wefq.Core(model, K, L, gamma=gamma, device=0, precisions=("fp64", "fp32"))
+        _cores[key] = wefq.Core(model, K, L, gamma=gamma, device=0, precisions=("fp64", "fp32", "bilinear"))
     return _cores[key]
 
 
@@ -121,3 +122,58 @@ def test_jvp_errors():
     assert L_.wefq_apply_J(core.handle, _lib.FP64, cp, None, op, 4, N, N, N, s) == _lib.WEFQ_EINVAL
     assert L_.wefq_apply_J(core.handle, _lib.FP64, cp, cp, op, 4, N, N, N - 1, s) == _lib.WEFQ_EINVAL
     assert L_.wefq_apply_J(core.handle, _lib.FP64, cp, cp, op, 0, N, N, N, s) == _lib.WEFQ_OK
+
+
+def qfg(core, f, g, prec):
+    return core.apply_Qfg(tensor(f, prec), tensor(g, prec), precision=prec).cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("K,L,model,gamma,B", [(3, 3, "hs", 1.0, 6), (4, 4, "vhs", 0.5, 9), (8, 8, "mm", 0.0, 3),
+                                               (2, 6, "vhs", 0.5, 4), (5, 2, "hs", 1.0, 3)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bilinear_matches_oracle(K, L, model, gamma, B, prec):
+    """Q(f, g) against the oracle's literal bilinear sum with the core before the zeroing
+    (the momentum and energy rows of Q(f, g) are not zero)."""
+    core = gpu_core(model, K, L, gamma)
+    f = synth.perturbed_maxwellian(K, L, B, seed=synth.BASE_SEED + 81 + K)
+    g = synth.perturbed_maxwellian(K, L, B, seed=synth.BASE_SEED + 91 + K)
+    g[:, 1:] += 0.1 * np.random.default_rng(K).standard_normal(g[:, 1:].shape)
+    say(f"[qfg] K={K} L={L} {model} B={B} {prec}")
+    f_in = tensor(f, prec).cpu().numpy().astype(np.float64)
+    g_in = tensor(g, prec).cpu().numpy().astype(np.float64)
+    ref = oapply.apply_bilinear(core_raw(K, L, gamma), coo(L), f_in, g_in, K)
+    got = qfg(core, f, g, prec)
+    assert rel_err(got, ref) < TOL[prec]
+    assert np.all(got[:, 0] == 0.0)
+    mom = invariant_indices(K, L)[1:]
+    assert np.abs(ref[:, mom]).max() > 1e-3 * np.abs(ref).max()      # the rows are really there
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_bilinear_identities(prec):
+    """Q(f, f) = Q(f); Q(f, g) + Q(g, f) = J(f) g; and for Maxwell molecules
+    Q(f, g) - Q(g, f) = f_000 g - g_000 f (b0 = 1/(4 pi)) on every row."""
+    K = L = 8
+    core = gpu_core("mm", K, L, 0.0)
+    f = synth.perturbed_maxwellian(K, L, 5, seed=21)
+    g = synth.perturbed_maxwellian(K, L, 5, seed=22)
+    g[:, 0] = 0.7
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    q = core.apply_Q(tensor(f, prec), precision=prec).cpu().numpy().astype(np.float64)
+    assert rel_err(qfg(core, f, f, prec), q) < tol
+    fg, gf = qfg(core, f, g, prec), qfg(core, g, f, prec)
+    assert rel_err(fg + gf, jvp(core, f, g, prec)) < tol
+    f_in = tensor(f, prec).cpu().numpy().astype(np.float64)
+    g_in = tensor(g, prec).cpu().numpy().astype(np.float64)
+    anti = f_in[:, :1] * g_in - g_in[:, :1] * f_in
+    anti[:, 0] = 0.0
+    assert rel_err(fg - gf, anti) < 10 * tol
+
+
+def test_bilinear_needs_prepared_tables():
+    core = wefq.Core("hs", 3, 3, device=0, precisions=("fp64",))
+    c = tensor(synth.perturbed_maxwellian(3, 3, 2, seed=1), "fp64")
+    with pytest.raises(wefq.WefqError) as err:
+        core.apply_Qfg(c, c, precision="fp64")
+    assert err.value.status == _lib.WEFQ_EINVAL
+    core.close()

@@ -240,6 +240,21 @@ def test_bilinear_form_and_jacobian():
     assert np.abs(asym).max() > 1e-3 * np.abs(j).max()
 
 
+def test_bilinear_antisymmetric_part_maxwell_molecules():
+    """For Maxwell molecules (B = b0 constant) the gain term is symmetric in the two inputs
+    and the loss term of Q(f, g) is -4 pi b0 g_000 f, so with the unzeroed core
+    Q(f, g) - Q(g, f) = 4 pi b0 (f_000 g - g_000 f) on every row, momentum and energy included."""
+    K, L = 3, 2
+    R = core_raw(K, L, 0.0)
+    T = coo(L)
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal(basis.num_modes(K, L))
+    g = rng.standard_normal(basis.num_modes(K, L))
+    lhs = apply.apply_bilinear(R, T, f, g, K) - apply.apply_bilinear(R, T, g, f, K)
+    rhs = 4 * math.pi * B0 * (f[0] * g - g[0] * f)
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+
+
 def test_rk_schemes_reach_bkw_at_their_order():
     """The BKW coefficients c(K(t)), K(t) = 1 - (1 - K0) exp(-t/6), solve the truncated
     system dc/dt = Q(c) exactly (Maxwell molecules, b0 = 1/(4 pi)), so the integration
