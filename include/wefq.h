@@ -82,6 +82,7 @@ typedef struct {
   int64_t device_bytes;   /* device memory held by the handle */
   double flop_alg_per_cell; /* 2 NK^2 N_G + 2 NK^3 N_S (Section 4.7, angular-first count) */
   double gamma, b0;
+  int64_t model;          /* wefq_model of the core */
 } wefq_core_info;
 
 /* Build the radial core R (Sections 3.2-3.3, 4.3-4.4) on the GPU in FP64 and the
@@ -99,6 +100,18 @@ wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info);
 /* Copy the zeroed FP64 core to host memory: R[c][k1][k2][k3], c in the paper's
  * channel order (l1 outer, l2, l3 inner), count = N_T * NK^3 doubles. */
 wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count);
+
+/* Write the core to a file: its parameters and the radial tensor before the invariant-row
+ * zeroing (N_T * NK^3 doubles, paper channel order), with a checksum, so that
+ * wefq_core_load can rebuild the handle without the quadrature.  Host only. */
+wefq_status wefq_core_save(wefq_handle h, const char* path);
+
+/* Build a core from a file written by wefq_core_save: model, gamma, b0, Kmax and Lmax come
+ * from the file; precisions (as in wefq_core_desc) and device are chosen here.  The
+ * tables and results are bitwise those of the saved core.  EINVAL for a missing,
+ * truncated or corrupted file (header, size and checksum are checked before any device
+ * work). */
+wefq_status wefq_core_load(const char* path, uint32_t precisions, int32_t device, void* stream, wefq_handle* out);
 
 /* Q = Q(f, f) for B independent cells (eq. full_discrete_sum, Section 4.5).
  * f and Q are device pointers, row-major [B][ld_f] / [B][ld_q], ld >= N,

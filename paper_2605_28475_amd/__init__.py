@@ -6,6 +6,7 @@ computation runs in the library's HIP kernels.  There is no CPU fallback: the
 calls raise if the HIP library is missing.
 """
 import ctypes
+import math
 
 import numpy as np
 
@@ -44,14 +45,35 @@ class Core:
         desc = _lib.CoreDesc(m, float(gamma), float(b0), int(K), int(L), mask, int(device))
         h = ctypes.c_void_p()
         _lib.check(_lib.lib().wefq_build_core(ctypes.byref(desc), _stream_ptr(stream, device), ctypes.byref(h)))
+        self._adopt(h, device)
+
+    def _adopt(self, h, device):
         self._h = h
         self.device = device
-        self.K, self.L = int(K), int(L)
-        self.model, self.gamma = m, float(gamma)
         info = _lib.CoreInfo()
         _lib.check(_lib.lib().wefq_core_info_get(h, ctypes.byref(info)))
         self.info = {name: getattr(info, name) for name, _ in _lib.CoreInfo._fields_}
         self.N = int(info.N)
+        self.K = int(info.NK) - 1
+        self.L = int(round(math.sqrt(int(info.NQ)))) - 1
+        self.model, self.gamma = int(info.model), float(info.gamma)
+
+    @classmethod
+    def load(cls, path, precisions=("fp64", "fp32", "bf16x3"), device=0, stream=None):
+        """A core rebuilt from a file written by save() (wefq_core_load), without the quadrature."""
+        mask = 0
+        for p in precisions:
+            mask |= PRECISIONS[p] if isinstance(p, str) else int(p)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().wefq_core_load(str(path).encode(), mask, int(device), _stream_ptr(stream, device),
+                                             ctypes.byref(h)))
+        core = cls.__new__(cls)
+        core._adopt(h, device)
+        return core
+
+    def save(self, path):
+        """Write the core (parameters and raw radial tensor) to a file (wefq_core_save)."""
+        _lib.check(_lib.lib().wefq_core_save(self._h, str(path).encode()))
 
     @property
     def handle(self):

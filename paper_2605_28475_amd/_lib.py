@@ -24,7 +24,7 @@ class CoreInfo(ctypes.Structure):
                 ("N_T_merged", ctypes.c_int64), ("N_G_merged", ctypes.c_int64),
                 ("N_S_merged", ctypes.c_int64), ("quad_nodes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("flop_alg_per_cell", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("b0", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("b0", ctypes.c_double), ("model", ctypes.c_int64)]
 
 
 class Segment(ctypes.Structure):
@@ -46,6 +46,9 @@ _SIGNATURES = [
     ("wefq_build_core", ctypes.c_int, [ctypes.POINTER(CoreDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     ("wefq_core_info_get", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(CoreInfo)]),
     ("wefq_core_download_R", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    ("wefq_core_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    ("wefq_core_load", ctypes.c_int, [ctypes.c_char_p, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
     ("wefq_apply_Q", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]),
     ("wefq_apply_J", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -128,8 +129,6 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
             Dm[(size_t)m * blk + ((size_t)k1 * NK + k2) * NK + k3] =
                 (ch.l1 == 0 && k1 == 0) ? 0.0 : sc * (Ra[((size_t)k1 * NK + k2) * NK + k3] - Rb[((size_t)k1 * NK + k3) * NK + k2]);
     }
-    h->R64raw.clear();
-    h->R64raw.shrink_to_fit();
   }
   std::vector<int> chan_begin(L + 2, 0);
   for (int m = 0; m < NTm; ++m) chan_begin[h->chans[mchan[m]].l1 + 1]++;
@@ -381,54 +380,69 @@ extern "C" {
 
 const char* wefq_last_error(void) { return g_last_error.c_str(); }
 
+// Validate the core parameters and make an empty handle with its channel and COO tables.
+static wefq_status new_core(int32_t model, double gamma_in, double b0, int32_t K, int32_t L, uint32_t precisions,
+                            int32_t device, wefq_core** out, std::vector<CooRow>& coo) {
+  *out = nullptr;
+  if (K < 0 || K > 16 || L < 0 || L > 16) return fail(WEFQ_EUNSUPPORTED, "Kmax and Lmax must lie in [0, 16]");
+  double gamma;
+  switch (model) {
+    case WEFQ_MAXWELL: gamma = 0.0; break;
+    case WEFQ_HARD_SPHERE: gamma = 1.0; break;
+    case WEFQ_VHS: gamma = gamma_in; break;
+    default: return fail(WEFQ_EINVAL, "unknown collision model");
+  }
+  if (!(gamma >= 0.0 && gamma <= 2.0)) return fail(WEFQ_EINVAL, "gamma must lie in [0, 2]");
+  unsigned prec = precisions ? precisions : (WEFQ_FP64 | WEFQ_FP32 | WEFQ_BF16X3);
+  if (prec & ~31u) return fail(WEFQ_EINVAL, "unknown precision bits");
+  if (prec & WEFQ_FP64_NAIVE) prec |= WEFQ_FP64;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(WEFQ_EHIP, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(WEFQ_EINVAL, "device ordinal out of range");
+  if (hipSetDevice(device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+  wefq_core* h = new (std::nothrow) wefq_core();
+  if (!h) return fail(WEFQ_ENOMEM, "host allocation failed");
+  h->device = device;
+  h->model = model;
+  h->K = K; h->L = L; h->NK = h->K + 1; h->NQ = (h->L + 1) * (h->L + 1);
+  h->N = h->NK * h->NQ;
+  h->gamma = gamma;
+  h->b0 = b0 > 0 ? b0 : 1.0 / (4.0 * 3.141592653589793238462643383279502884);
+  h->precisions = prec;
+  h->chans = enumerate_channels(h->L);
+  h->NT = (int)h->chans.size();
+  coo = build_coo(h->L);
+  h->NG = (int)coo.size();
+  std::vector<char> seen((size_t)h->NT * h->NQ, 0);
+  int ns = 0;
+  for (auto& r : coo) if (!seen[(size_t)r.c * h->NQ + r.q1]) { seen[(size_t)r.c * h->NQ + r.q1] = 1; ++ns; }
+  h->NS = ns;
+  *out = h;
+  return WEFQ_OK;
+}
+
+// From the raw core in h->R64: keep a copy (bilinear tables, serialization), zero the
+// invariant rows (Section 4.4) and prepare the device tables.
+static wefq_status finish_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t s, wefq_handle* out) {
+  h->R64raw = h->R64;
+  zero_invariants(h);
+  if (!prepare_apply_tables(h, coo, s)) { free_core(h); return WEFQ_ENOMEM; }
+  *out = h;
+  return WEFQ_OK;
+}
+
 wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handle* out) {
   try {
     if (!desc || !out) return fail(WEFQ_EINVAL, "null descriptor or output pointer");
     *out = nullptr;
-    if (desc->Kmax < 0 || desc->Kmax > 16 || desc->Lmax < 0 || desc->Lmax > 16)
-      return fail(WEFQ_EUNSUPPORTED, "Kmax and Lmax must lie in [0, 16]");
-    double gamma;
-    switch (desc->model) {
-      case WEFQ_MAXWELL: gamma = 0.0; break;
-      case WEFQ_HARD_SPHERE: gamma = 1.0; break;
-      case WEFQ_VHS: gamma = desc->gamma; break;
-      default: return fail(WEFQ_EINVAL, "unknown collision model");
-    }
-    if (!(gamma >= 0.0 && gamma <= 2.0)) return fail(WEFQ_EINVAL, "gamma must lie in [0, 2]");
-    unsigned prec = desc->precisions ? desc->precisions : (WEFQ_FP64 | WEFQ_FP32 | WEFQ_BF16X3);
-    if (prec & ~31u) return fail(WEFQ_EINVAL, "unknown precision bits");
-    if (prec & WEFQ_FP64_NAIVE) prec |= WEFQ_FP64;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(WEFQ_EHIP, "no HIP device available");
-    if (desc->device < 0 || desc->device >= ndev) return fail(WEFQ_EINVAL, "device ordinal out of range");
-    if (hipSetDevice(desc->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
-    wefq_core* h = new (std::nothrow) wefq_core();
-    if (!h) return fail(WEFQ_ENOMEM, "host allocation failed");
-    h->device = desc->device;
-    h->K = desc->Kmax; h->L = desc->Lmax; h->NK = h->K + 1; h->NQ = (h->L + 1) * (h->L + 1);
-    h->N = h->NK * h->NQ;
-    h->gamma = gamma;
-    h->b0 = desc->b0 > 0 ? desc->b0 : 1.0 / (4.0 * 3.141592653589793238462643383279502884);
-    h->precisions = prec;
-    h->chans = enumerate_channels(h->L);
-    h->NT = (int)h->chans.size();
-    std::vector<CooRow> coo = build_coo(h->L);
-    h->NG = (int)coo.size();
-    {
-      std::vector<char> seen((size_t)h->NT * h->NQ, 0);
-      int ns = 0;
-      for (auto& r : coo) if (!seen[(size_t)r.c * h->NQ + r.q1]) { seen[(size_t)r.c * h->NQ + r.q1] = 1; ++ns; }
-      h->NS = ns;
-    }
+    wefq_core* h = nullptr;
+    std::vector<CooRow> coo;
+    wefq_status st = new_core(desc->model, desc->gamma, desc->b0, desc->Kmax, desc->Lmax, desc->precisions,
+                              desc->device, &h, coo);
+    if (st != WEFQ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if (!build_radial_core(h, coo, s)) { free_core(h); return WEFQ_EHIP; }
-    // the bilinear form keeps the momentum and energy rows that the zeroing removes
-    // (they are antisymmetric in the two inputs, so they vanish for Q(f, f) only)
-    if (prec & WEFQ_PREP_BILINEAR) h->R64raw = h->R64;
-    zero_invariants(h);
-    if (!prepare_apply_tables(h, coo, s)) { free_core(h); return WEFQ_ENOMEM; }
-    *out = h;
-    return WEFQ_OK;
+    return finish_core(h, coo, s, out);
   } catch (const std::exception& e) {
     return fail(WEFQ_EINVAL, std::string("exception in core build: ") + e.what());
   } catch (...) {
@@ -446,6 +460,7 @@ wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info) {
   double nk = h->NK;
   info->flop_alg_per_cell = 2.0 * nk * nk * h->NG + 2.0 * nk * nk * nk * h->NS;
   info->gamma = h->gamma; info->b0 = h->b0;
+  info->model = h->model;
   return WEFQ_OK;
 }
 
@@ -454,6 +469,81 @@ wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count) {
   if (count != (int64_t)h->R64.size()) return fail(WEFQ_EINVAL, "count must equal N_T * NK^3");
   std::memcpy(host_R, h->R64.data(), h->R64.size() * sizeof(double));
   return WEFQ_OK;
+}
+
+// ---- serialization: the raw radial core and its parameters
+//
+// File layout (native byte order): CoreFileHeader, then N_T * NK^3 doubles of the core
+// before the invariant-row zeroing, [c][k1][k2][k3] in the paper's channel order.  The
+// checksum is the 64-bit FNV-1a hash of the payload bytes.
+struct CoreFileHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int32_t model, K, L, NT, NK, pad;
+  double gamma, b0;
+  int64_t quad_nodes;
+  uint64_t count, checksum;
+};
+static const char kCoreMagic[8] = {'W', 'E', 'F', 'Q', 'C', 'O', 'R', 'E'};
+
+static uint64_t fnv1a(const void* data, size_t n) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  uint64_t hsh = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) { hsh ^= p[i]; hsh *= 1099511628211ull; }
+  return hsh;
+}
+
+wefq_status wefq_core_save(wefq_handle h, const char* path) {
+  if (!h || !path) return fail(WEFQ_EINVAL, "null handle or path");
+  if (h->R64raw.size() != h->R64.size()) return fail(WEFQ_EINVAL, "the core holds no raw radial tensor");
+  CoreFileHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  std::memcpy(hd.magic, kCoreMagic, 8);
+  hd.version = 1;
+  hd.header_bytes = sizeof(CoreFileHeader);
+  hd.model = h->model; hd.K = h->K; hd.L = h->L; hd.NT = h->NT; hd.NK = h->NK;
+  hd.gamma = h->gamma; hd.b0 = h->b0; hd.quad_nodes = h->quad_nodes;
+  hd.count = h->R64raw.size();
+  hd.checksum = fnv1a(h->R64raw.data(), h->R64raw.size() * sizeof(double));
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return fail(WEFQ_EINVAL, std::string("cannot open for writing: ") + path);
+  bool ok = std::fwrite(&hd, sizeof(hd), 1, fp) == 1 &&
+            std::fwrite(h->R64raw.data(), sizeof(double), h->R64raw.size(), fp) == h->R64raw.size();
+  ok = (std::fclose(fp) == 0) && ok;
+  if (!ok) return fail(WEFQ_EINVAL, std::string("write failed: ") + path);
+  return WEFQ_OK;
+}
+
+wefq_status wefq_core_load(const char* path, uint32_t precisions, int32_t device, void* stream, wefq_handle* out) {
+  try {
+    if (!path || !out) return fail(WEFQ_EINVAL, "null path or output pointer");
+    *out = nullptr;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(WEFQ_EINVAL, std::string("cannot open: ") + path);
+    CoreFileHeader hd;
+    std::vector<double> raw;
+    bool ok = std::fread(&hd, sizeof(hd), 1, fp) == 1 && std::memcmp(hd.magic, kCoreMagic, 8) == 0 &&
+              hd.version == 1 && hd.header_bytes == sizeof(CoreFileHeader) && hd.K >= 0 && hd.K <= 16 &&
+              hd.L >= 0 && hd.L <= 16 && hd.NK == hd.K + 1 &&
+              hd.count == (uint64_t)hd.NT * hd.NK * hd.NK * hd.NK && hd.NT > 0;
+    if (ok) {
+      raw.resize(hd.count);
+      ok = std::fread(raw.data(), sizeof(double), raw.size(), fp) == raw.size() && std::fgetc(fp) == EOF &&
+           fnv1a(raw.data(), raw.size() * sizeof(double)) == hd.checksum;
+    }
+    std::fclose(fp);
+    if (!ok) return fail(WEFQ_EINVAL, std::string("not a valid core file (header, size or checksum): ") + path);
+    wefq_core* h = nullptr;
+    std::vector<CooRow> coo;
+    wefq_status st = new_core(hd.model, hd.gamma, hd.b0, hd.K, hd.L, precisions, device, &h, coo);
+    if (st != WEFQ_OK) return st;
+    if (h->NT != hd.NT) { free_core(h); return fail(WEFQ_EINVAL, "channel count does not match the truncation"); }
+    h->R64 = std::move(raw);
+    h->quad_nodes = hd.quad_nodes;
+    return finish_core(h, coo, (hipStream_t)stream, out);
+  } catch (const std::exception& e) {
+    return fail(WEFQ_EINVAL, std::string("exception in core load: ") + e.what());
+  }
 }
 
 static wefq_status check_batch(wefq_handle h, int32_t precision, const void* a, const void* b, int64_t B,

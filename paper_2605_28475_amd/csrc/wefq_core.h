@@ -11,6 +11,7 @@
 
 struct wefq_core {
   int device = 0;
+  int model = 0;
   int K = 0, L = 0, NK = 0, NQ = 0, N = 0;
   int NT = 0, NG = 0, NS = 0;          // paper counts
   int NTm = 0, NGm = 0, NSm = 0;       // merged counts
@@ -20,7 +21,7 @@ struct wefq_core {
   int64_t device_bytes = 0;
   std::vector<wefq::Channel> chans;
   std::vector<double> R64;             // host copy, zeroed, [c][k1][k2][k3]
-  std::vector<double> R64raw;          // before the zeroing (bilinear-form tables only; freed after use)
+  std::vector<double> R64raw;          // before the invariant-row zeroing (bilinear tables, serialization)
 
   // FP64 plain path: COO rows grouped by q1 (CSR), paper channel ids
   double* dR64 = nullptr;

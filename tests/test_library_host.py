@@ -82,3 +82,20 @@ def test_error_paths_without_device():
                                x.ctypes.data_as(ctypes.c_void_p)) == _lib.WEFQ_EINVAL
     with pytest.raises(wefq.WefqError):
         wefq.host_gauss(1, 0)
+
+
+def test_core_load_rejects_bad_files_before_device_work(tmp_path):
+    """wefq_core_load checks header, size and checksum before any HIP call."""
+    L_ = _lib.lib()
+    h = ctypes.c_void_p()
+    missing = str(tmp_path / "missing.wefq").encode()
+    assert L_.wefq_core_load(missing, 0, 0, None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    garbage = tmp_path / "garbage.wefq"
+    garbage.write_bytes(b"not a core file" * 10)
+    assert L_.wefq_core_load(str(garbage).encode(), 0, 0, None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    assert b"not a valid core file" in L_.wefq_last_error()
+    empty = tmp_path / "empty.wefq"
+    empty.write_bytes(b"")
+    assert L_.wefq_core_load(str(empty).encode(), 0, 0, None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    assert L_.wefq_core_save(None, missing) == _lib.WEFQ_EINVAL
+    assert not h.value
