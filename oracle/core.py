@@ -21,6 +21,10 @@ core_exact         evaluates the same sum directly.  sum_m g C is a rotation
     the test function, int dn phi_{k l m}(G + r n), equals h_kl(|G|, r) Y_lm(G_hat)
     (it commutes with rotations), and h_kl is a 1-D Gauss-Legendre integral
     (gain="funk_hecke"); gain="sphere" integrates over n directly instead.
+With an angular factor, B = b0 u^gamma beta(cos chi) and cos chi = u_hat . n
+(Sections 2.1, 4.3), the gain average int dn beta(u_hat . n) phi(G + r n) is not
+a function of G alone, so only gain="sphere" applies: it weights the sphere
+rule by beta at every node, and the loss by int dn beta(u_hat . n).
 No quantity here is truncated or regularized: the result is exact up to FP64
 rounding for any gamma >= 0.
 """
@@ -32,7 +36,7 @@ from scipy.special import roots_genlaguerre, roots_hermite, roots_legendre
 
 from .basis import basis_all, num_modes, q_index, radial, real_sh_all, real_sph_harm
 from .gaunt import coo, l_of_q, sphere_rule
-from .weakform import B0_DEFAULT
+from .weakform import B0_DEFAULT, angular_factor
 
 
 def core_from_tensor(C, K, L, table=None):
@@ -97,12 +101,19 @@ def _gain_h(K, L, Gn, r):
     return h
 
 
-def core_exact(K, L, gamma, b0=B0_DEFAULT, gain="funk_hecke", table=None,
-               chunk=8192, subset=None):
+def core_exact(K, L, gamma, b0=B0_DEFAULT, gain="auto", table=None,
+               chunk=8192, subset=None, beta=None):
     """R[c, k1, k2, k3] (no zeroing) by the exact reduced quadrature.
 
     subset: optional list of channel indices; other channels are left zero.
+    beta:   Legendre coefficients of the angular factor beta(cos chi), or None
+            for the isotropic kernel.
     """
+    if gain == "auto":
+        gain = "funk_hecke" if beta is None else "sphere"
+    if beta is not None and gain != "sphere":
+        raise ValueError("an angular factor needs gain='sphere'")
+    J = 0 if beta is None else len(beta) - 1
     table = table or coo(L)
     chans = table["channels"]
     NT, NK = len(chans), K + 1
@@ -112,6 +123,8 @@ def core_exact(K, L, gamma, b0=B0_DEFAULT, gain="funk_hecke", table=None,
     W = W * b0 * (2 * math.pi) ** -3
     vn, wn, w_f, G_f, r = _frames(gp, gz, s)
     P = len(W)
+    v_f = np.stack([np.zeros_like(vn), np.zeros_like(vn), vn], axis=-1)
+    uhat = (v_f - w_f) / (2.0 * r)[:, None]                    # relative-velocity direction
     Rv = np.stack([np.stack([radial(k, l, vn) for k in range(NK)], -1)
                    for l in range(L + 1)], 1)                  # (P, L+1, NK)
     Rw = np.stack([np.stack([radial(k, l, wn) for k in range(NK)], -1)
@@ -129,6 +142,7 @@ def core_exact(K, L, gamma, b0=B0_DEFAULT, gain="funk_hecke", table=None,
     SL = csr_matrix((g[keepL] * Yz[q1[keepL]] * Yz[q2[keepL]],
                      (np.arange(keepL.sum()), cz[keepL])), shape=(keepL.sum(), NT))
     JL = np.asarray((SL.T @ Yw[:, q3[keepL]].T).T)
+    lossw = np.full(P, 4 * math.pi)                             # int dn beta(u_hat . n)
     if gain == "funk_hecke":
         Gn = np.linalg.norm(G_f, axis=1)
         Hrad = _gain_h(K, L, Gn, r)                            # (P, L+1, NK)
@@ -144,14 +158,16 @@ def core_exact(K, L, gamma, b0=B0_DEFAULT, gain="funk_hecke", table=None,
         def gain_block(cs):
             return J[:, cs, None] * Hrad[:, lc[cs], :]
     elif gain == "sphere":
-        Nn, WN = sphere_rule(2 * K + L)
+        Nn, WN = sphere_rule(2 * K + L + J)
         N = num_modes(K, L)
         Hm = np.empty((P, (L + 1) ** 2, NK))
         for p0 in range(0, P, 64):
             sl = slice(p0, p0 + 64)
             pts = G_f[sl][:, None, :] + r[sl][:, None, None] * Nn[None]
-            Hm[sl] = np.einsum("pnj,n->pj", basis_all(K, L, pts.reshape(-1, 3))
-                               .reshape(len(pts), len(WN), N), WN).reshape(-1, NQ_of(L), NK)
+            Wn = angular_factor(beta, uhat[sl] @ Nn.T) * WN[None, :]   # beta(u_hat . n) dn
+            lossw[sl] = Wn.sum(axis=1)
+            Hm[sl] = np.einsum("pnj,pn->pj", basis_all(K, L, pts.reshape(-1, 3))
+                               .reshape(len(pts), len(WN), N), Wn).reshape(-1, NQ_of(L), NK)
         fac = (g[keep] * Yz[q2[keep]]) * Yw[:, q3[keep]]               # (P, z)
         Xg_all = np.zeros((P, NT, NK))
         for zi, (c, qa) in enumerate(zip(cz[keep], q1[keep])):
@@ -168,7 +184,7 @@ def core_exact(K, L, gamma, b0=B0_DEFAULT, gain="funk_hecke", table=None,
             pairs.setdefault((l2, l3), []).append(ci)
     for (l2, l3), cs in pairs.items():
         cs = np.array(cs)
-        X = gain_block(cs) - 4 * math.pi * JL[:, cs, None] * Rv[:, lc[cs], :]
+        X = gain_block(cs) - lossw[:, None, None] * JL[:, cs, None] * Rv[:, lc[cs], :]
         X *= W[:, None, None]
         E = (Rv[:, l2, :, None] * Rw[:, l3, None, :]).reshape(P, NK * NK)
         R[cs] = (X.reshape(P, len(cs) * NK).T @ E).reshape(len(cs), NK, NK, NK)

@@ -11,14 +11,15 @@ def coo(L):
 
 
 @functools.lru_cache(maxsize=None)
-def core_zeroed(K, L, gamma, b0=1.0 / (4 * math.pi)):
+def core_zeroed(K, L, gamma, b0=1.0 / (4 * math.pi), beta=None):
+    """beta: a tuple of Legendre coefficients of the angular factor, or None."""
     T = coo(L)
-    return core.zero_invariants(core.core_exact(K, L, gamma, b0=b0, table=T), T["channels"])
+    return core.zero_invariants(core_raw(K, L, gamma, b0, beta), T["channels"])
 
 
 @functools.lru_cache(maxsize=None)
-def core_raw(K, L, gamma, b0=1.0 / (4 * math.pi)):
-    return core.core_exact(K, L, gamma, b0=b0, table=coo(L))
+def core_raw(K, L, gamma, b0=1.0 / (4 * math.pi), beta=None):
+    return core.core_exact(K, L, gamma, b0=b0, table=coo(L), beta=None if beta is None else list(beta))
 
 
 def golden(name):

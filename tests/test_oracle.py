@@ -336,3 +336,91 @@ def test_rotation_equivariance_of_factorized_sum():
     Qc = apply.apply_q(R, T, c, K)
     Qr = apply.apply_q(R, T, rotate(c, K, L, blocks), K)
     assert np.abs(Qr - rotate(Qc, K, L, blocks)).max() < 1e-14 * np.abs(Qc).max() * 10
+
+
+# ---------------------------------------------------------------- anisotropic scattering
+BETA = (1.0, 0.5, 0.3, 0.1)          # beta(t) = 1 + 0.5 P1 + 0.3 P2 + 0.1 P3 > 0 on [-1, 1]
+
+
+def test_anisotropic_core_matches_bruteforce_definition():
+    """B = b0 u^gamma beta(cos chi): the reduced quadrature (relative-velocity frame, beta-weighted
+    sphere rule per node) equals the 8-D definition taken literally (Section 2.3)."""
+    K, L, gamma = 2, 2, 1.0
+    T = coo(L)
+    Rb = core.core_from_tensor(weakform.c_tensor_bruteforce(K, L, gamma, beta=BETA), K, L, T)
+    Re = core_raw(K, L, gamma, beta=BETA)
+    assert np.abs(Rb - Re).max() < 1e-14 * np.abs(Rb).max()
+    # the angular factor really changed the core; beta = 1 is the isotropic kernel
+    assert np.abs(Re - core_raw(K, L, gamma)).max() > 0.1 * np.abs(Re).max()
+    iso = core.core_exact(K, L, gamma, table=T, beta=[1.0])
+    assert np.abs(iso - core_raw(K, L, gamma)).max() < 1e-14 * np.abs(iso).max()
+
+
+def _wcu_beta(k, l, beta, b0=B0):
+    t, w = roots_legendre(40)
+    c, s = np.sqrt((1 + t) / 2), np.sqrt((1 - t) / 2)
+    f = c ** (2 * k + l) * eval_legendre(l, c) + s ** (2 * k + l) * eval_legendre(l, s) - 1 - (k == 0 and l == 0)
+    bt = sum(bj * eval_legendre(j, t) for j, bj in enumerate(beta))
+    return 2 * math.pi * b0 * float(w @ (bt * f))
+
+
+def test_anisotropic_maxwell_spectrum_wang_chang_uhlenbeck():
+    """Maxwell molecules with any angular factor: the linearized operator is diagonal in the
+    Burnett basis with lambda_kl = 2 pi b0 int beta(t) [c^{2k+l} P_l(c) + s^{2k+l} P_l(s)
+    - 1 - delta_k0 delta_l0] dt, c = cos(chi/2), s = sin(chi/2) (Wang Chang and Uhlenbeck)."""
+    K, L = 3, 4
+    Lm = _linearized(core_zeroed(K, L, 0.0, beta=BETA), coo(L)["channels"], K, L)
+    lam = np.array([_wcu_beta(k, l, BETA) for k, l, m in basis.mode_table(K, L)])
+    assert np.abs(Lm - np.diag(lam)).max() < 1e-14
+    assert np.abs(lam - np.array([_wcu(k, l) for k, l, m in basis.mode_table(K, L)])).max() > 0.02
+
+
+def test_anisotropic_only_even_part_enters_q():
+    """Swapping the post-collision velocities (n -> -n) turns beta(t) into beta(-t) and leaves
+    Q(f, f) unchanged, while the unsymmetrized core and Q(f, g) do change."""
+    K, L = 3, 3
+    flip = tuple(b * (-1) ** j for j, b in enumerate(BETA))
+    T = coo(L)
+    rng = np.random.default_rng(7)
+    c = np.zeros((2, basis.num_modes(K, L))); c[:, 0] = 1.0
+    c += 0.1 * rng.standard_normal(c.shape)
+    qa = apply.apply_q(core_zeroed(K, L, 0.5, beta=BETA), T, c, K)
+    qb = apply.apply_q(core_zeroed(K, L, 0.5, beta=flip), T, c, K)
+    assert np.abs(qa - qb).max() < 1e-14 * np.abs(qa).max()
+    Ra, Rb = core_raw(K, L, 0.5, beta=BETA), core_raw(K, L, 0.5, beta=flip)
+    assert np.abs(Ra - Rb).max() > 0.1 * np.abs(Ra).max()
+    ga = apply.apply_bilinear(Ra, T, c[0], c[1], K)
+    gb = apply.apply_bilinear(Rb, T, c[0], c[1], K)
+    assert np.abs(ga - gb).max() > 1e-3 * np.abs(ga).max()
+
+
+def test_anisotropic_conservation_before_zeroing():
+    """Mass, momentum and energy are collision invariants for any B: with the unzeroed core
+    the five invariant rows of Q vanish to rounding, and so does Q of the Maxwellian."""
+    K, L = 3, 3
+    R = core_raw(K, L, 1.0, beta=BETA)
+    T = coo(L)
+    c = np.zeros(basis.num_modes(K, L)); c[0] = 1.0
+    e0 = c.copy()
+    c += 0.1 * np.random.default_rng(8).standard_normal(c.shape)
+    Q = apply.apply_q(R, T, c, K)
+    inv = [basis.mode_index(K, 0, 0, 0), basis.mode_index(K, 1, 0, 0)] + \
+        [basis.mode_index(K, 0, 1, m) for m in (-1, 0, 1)]
+    assert np.abs(Q[inv]).max() < 1e-14 * np.abs(Q).max()
+    assert np.abs(apply.apply_q(R, T, e0, K)).max() < 1e-14
+
+
+def test_anisotropic_maxwell_antisymmetric_part():
+    """Maxwell molecules with an even angular factor: the gain of Q(f, g) is symmetric in
+    the inputs and the loss is -4 pi b0 beta_0 g_000 f, so
+    Q(f, g) - Q(g, f) = 4 pi b0 beta_0 (f_000 g - g_000 f) with the unzeroed core."""
+    K, L = 3, 2
+    beta = (0.8, 0.0, 0.4, 0.0, 0.2)
+    R = core_raw(K, L, 0.0, beta=beta)
+    T = coo(L)
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(basis.num_modes(K, L))
+    g = rng.standard_normal(basis.num_modes(K, L))
+    lhs = apply.apply_bilinear(R, T, f, g, K) - apply.apply_bilinear(R, T, g, f, K)
+    rhs = 4 * math.pi * B0 * beta[0] * (f[0] * g - g[0] * f)
+    assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
