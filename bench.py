@@ -102,11 +102,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16x3 comparison legs")
-    ap.add_argument("--workload", choices=["k12", "uneven", "serve", "rk", "jvp"], default="k12",
+    ap.add_argument("--workload", choices=["k12", "uneven", "serve", "rk", "jvp", "build"], default="k12",
                     help="k12: the headline batch; uneven: one persistent launch over a mix of cores; "
                          "serve: continuous-batching server under Poisson arrivals; "
                          "rk: batched RK4 time stepping (anisotropic stress relaxation, hard spheres); "
-                         "jvp: Jacobian-vector products J(c) d on the headline batch")
+                         "jvp: Jacobian-vector products J(c) d on the headline batch; "
+                         "build: radial core build times, isotropic and with angular factors, and reload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of f (known byte count) for counter scaling")
     args = ap.parse_args()
@@ -128,6 +129,8 @@ def main():
         return bench_rk(args, torch, wefq, synth)
     if args.workload == "jvp":
         return bench_jvp(args, torch, wefq, synth)
+    if args.workload == "build":
+        return bench_build(args, torch, wefq)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -227,6 +230,43 @@ def main():
         out["cpu_baseline"] = cpu_baseline(K, L, gamma, c, args.cpu_budget)
     out["host_cpu"] = {"cpu_count": os.cpu_count()}
     core.close()
+    print(json.dumps(out), flush=True)
+
+
+# angular factors of the build workload: Legendre coefficients of beta(cos chi)
+BUILD_BETAS = {"isotropic": None, "deg3": (1.0, 0.5, 0.3, 0.1),
+               "deg8": (1.0, 0.8, 0.55, 0.35, 0.2, 0.1, 0.05, 0.02, 0.005)}
+
+
+def bench_build(args, torch, wefq):
+    """Wall time of wefq_build_core (FP64 quadrature on the GPU plus the apply tables of all
+    precisions) for hard spheres at K = L = 8, 12, 16, isotropic and with two angular factors,
+    and of wefq_core_load of the same core from a file."""
+    import tempfile
+    torch.cuda.set_device(0)
+    wefq.Core("hs", 2, 2, device=0, precisions=("fp64",)).close()      # context and module load
+    rows = []
+    with tempfile.TemporaryDirectory() as tmp:
+        for K in (8, 12, 16):
+            for name, beta in BUILD_BETAS.items():
+                log(f"[build] K=L={K} {name}")
+                t0 = time.perf_counter()
+                core = wefq.Core("hs", K, K, device=0, beta=beta)
+                t_build = time.perf_counter() - t0
+                row = {"K": K, "L": K, "beta": name, "build_s": t_build,
+                       "quad_nodes": core.info["quad_nodes"], "device_bytes": core.info["device_bytes"]}
+                if beta is None:
+                    path = os.path.join(tmp, f"k{K}.wefq")
+                    core.save(path)
+                    t0 = time.perf_counter()
+                    wefq.Core.load(path, device=0).close()
+                    row["load_s"] = time.perf_counter() - t0
+                core.close()
+                rows.append(row)
+    k12 = [r for r in rows if r["K"] == 12 and r["beta"] == "isotropic"][0]
+    out = {"metric": "radial core build time, hard spheres, K = L = 12 (FP64 on the GPU)",
+           "value": k12["build_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+           "dtype": "f64", "data": "synthetic", "config": {"workload": "core_build_hs"}, "builds": rows}
     print(json.dumps(out), flush=True)
 
 

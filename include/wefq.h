@@ -61,9 +61,21 @@ typedef enum {
                              FP64 / FP32 precisions requested */
 } wefq_precision;
 
-/* Descriptor of a radial core.  The collision kernel is B(u, cos chi) = b0 u^gamma
- * (isotropic, Grad cut-off; Section 2.1).  b0 <= 0 selects b0 = 1/(4 pi), for which
- * int B du' = u^gamma.  precisions is a bitmask of wefq_precision values to prepare. */
+/* Most Legendre coefficients of an angular factor (degree <= 32). */
+#define WEFQ_MAX_BETA 33
+
+/* Descriptor of a radial core.  The collision kernel (Section 2.1, Grad cut-off) is
+ *   B(u, cos chi) = b0 u^gamma beta(cos chi),  beta(t) = sum_{j < n_beta} beta[j] P_j(t),
+ * with chi the deflection angle between the pre- and post-collision relative velocities
+ * and P_j the Legendre polynomials.  n_beta = 0 (beta may then be NULL) is the isotropic
+ * kernel beta = 1; a zero-initialized descriptor tail selects it.  b0 <= 0 selects
+ * b0 = 1/(4 pi), for which int B du' = 4 pi b0 beta[0] u^gamma = beta[0] u^gamma.  beta is
+ * read during the call and not kept; physical kernels have beta >= 0 on [-1, 1], which is
+ * not checked.  With n_beta >= 1 the gain sphere average is integrated by a direct
+ * beta-weighted rule at every node (exact for a polynomial beta), which costs more build
+ * time than the isotropic closed form.  Only the even part of beta enters Q(f, f); the
+ * whole of it enters the bilinear form Q(f, g).  precisions is a bitmask of
+ * wefq_precision values to prepare. */
 typedef struct {
   int32_t model;
   double gamma;           /* used when model == WEFQ_VHS; must be in [0, 2] */
@@ -72,6 +84,8 @@ typedef struct {
   int32_t Lmax;           /* 0 <= Lmax <= 16 */
   uint32_t precisions;
   int32_t device;         /* HIP device ordinal */
+  int32_t n_beta;         /* 0 <= n_beta <= WEFQ_MAX_BETA; finite coefficients */
+  const double* beta;     /* host pointer, n_beta doubles (Legendre coefficients) */
 } wefq_core_desc;
 
 typedef struct {
@@ -83,6 +97,8 @@ typedef struct {
   double flop_alg_per_cell; /* 2 NK^2 N_G + 2 NK^3 N_S (Section 4.7, angular-first count) */
   double gamma, b0;
   int64_t model;          /* wefq_model of the core */
+  int64_t n_beta;         /* angular factor: Legendre coefficients beta[0 .. n_beta) */
+  double beta[WEFQ_MAX_BETA];
 } wefq_core_info;
 
 /* Build the radial core R (Sections 3.2-3.3, 4.3-4.4) on the GPU in FP64 and the
@@ -92,7 +108,8 @@ typedef struct {
  * (Section 4.4).  Synchronous: returns when the handle is ready.  stream may be
  * NULL (the default stream).  On success *out owns all device memory of the core;
  * release it with wefq_destroy.  The handle is read-only afterwards and may be
- * used concurrently from several streams. */
+ * used concurrently from several streams.  EINVAL for n_beta outside
+ * [0, WEFQ_MAX_BETA], a NULL beta with n_beta > 0 or a non-finite coefficient. */
 wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handle* out);
 
 wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info);
@@ -106,8 +123,8 @@ wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count);
  * wefq_core_load can rebuild the handle without the quadrature.  Host only. */
 wefq_status wefq_core_save(wefq_handle h, const char* path);
 
-/* Build a core from a file written by wefq_core_save: model, gamma, b0, Kmax and Lmax come
- * from the file; precisions (as in wefq_core_desc) and device are chosen here.  The
+/* Build a core from a file written by wefq_core_save: model, gamma, b0, the angular
+ * factor, Kmax and Lmax come from the file; precisions (as in wefq_core_desc) and device are chosen here.  The
  * tables and results are bitwise those of the saved core.  EINVAL for a missing,
  * truncated or corrupted file (header, size and checksum are checked before any device
  * work). */

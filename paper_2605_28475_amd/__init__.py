@@ -32,17 +32,23 @@ def _stream_ptr(stream, device):
 
 
 class Core:
-    """A built radial core (wefq_build_core) resident on one GPU."""
+    """A built radial core (wefq_build_core) resident on one GPU.
+
+    beta: Legendre coefficients of the angular factor of B(u, cos chi) = b0 u^gamma
+    beta(cos chi), or None for the isotropic kernel."""
 
     def __init__(self, model, K, L, gamma=None, b0=0.0, precisions=("fp64", "fp32", "bf16x3"),
-                 device=0, stream=None):
+                 device=0, stream=None, beta=None):
         m = MODELS[model] if isinstance(model, str) else int(model)
         if gamma is None:
             gamma = {MAXWELL: 0.0, HARD_SPHERE: 1.0}.get(m, 0.5)
         mask = 0
         for p in precisions:
             mask |= PRECISIONS[p] if isinstance(p, str) else int(p)
-        desc = _lib.CoreDesc(m, float(gamma), float(b0), int(K), int(L), mask, int(device))
+        coef = [] if beta is None else [float(b) for b in beta]
+        arr = (ctypes.c_double * max(1, len(coef)))(*coef)
+        desc = _lib.CoreDesc(m, float(gamma), float(b0), int(K), int(L), mask, int(device),
+                             len(coef), ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)) if coef else None)
         h = ctypes.c_void_p()
         _lib.check(_lib.lib().wefq_build_core(ctypes.byref(desc), _stream_ptr(stream, device), ctypes.byref(h)))
         self._adopt(h, device)
@@ -52,11 +58,13 @@ class Core:
         self.device = device
         info = _lib.CoreInfo()
         _lib.check(_lib.lib().wefq_core_info_get(h, ctypes.byref(info)))
-        self.info = {name: getattr(info, name) for name, _ in _lib.CoreInfo._fields_}
+        self.info = {name: getattr(info, name) for name, _ in _lib.CoreInfo._fields_ if name != "beta"}
         self.N = int(info.N)
         self.K = int(info.NK) - 1
         self.L = int(round(math.sqrt(int(info.NQ)))) - 1
         self.model, self.gamma = int(info.model), float(info.gamma)
+        nb = int(info.n_beta)
+        self.beta = tuple(float(info.beta[j]) for j in range(nb)) if nb else None
 
     @classmethod
     def load(cls, path, precisions=("fp64", "fp32", "bf16x3"), device=0, stream=None):

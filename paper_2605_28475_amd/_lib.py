@@ -12,10 +12,14 @@ RK_EULER, RK_HEUN, RK_SSP3, RK_CLASSIC4 = 1, 2, 3, 4
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED", 5: "EBUDGET"}
 
 
+MAX_BETA = 33          # WEFQ_MAX_BETA
+
+
 class CoreDesc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("gamma", ctypes.c_double), ("b0", ctypes.c_double),
                 ("Kmax", ctypes.c_int32), ("Lmax", ctypes.c_int32),
-                ("precisions", ctypes.c_uint32), ("device", ctypes.c_int32)]
+                ("precisions", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("n_beta", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double))]
 
 
 class CoreInfo(ctypes.Structure):
@@ -24,7 +28,8 @@ class CoreInfo(ctypes.Structure):
                 ("N_T_merged", ctypes.c_int64), ("N_G_merged", ctypes.c_int64),
                 ("N_S_merged", ctypes.c_int64), ("quad_nodes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("flop_alg_per_cell", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("b0", ctypes.c_double), ("model", ctypes.c_int64)]
+                ("gamma", ctypes.c_double), ("b0", ctypes.c_double), ("model", ctypes.c_int64),
+                ("n_beta", ctypes.c_int64), ("beta", ctypes.c_double * MAX_BETA)]
 
 
 class Segment(ctypes.Structure):

@@ -382,9 +382,14 @@ const char* wefq_last_error(void) { return g_last_error.c_str(); }
 
 // Validate the core parameters and make an empty handle with its channel and COO tables.
 static wefq_status new_core(int32_t model, double gamma_in, double b0, int32_t K, int32_t L, uint32_t precisions,
-                            int32_t device, wefq_core** out, std::vector<CooRow>& coo) {
+                            int32_t device, int32_t n_beta, const double* beta, wefq_core** out,
+                            std::vector<CooRow>& coo) {
   *out = nullptr;
   if (K < 0 || K > 16 || L < 0 || L > 16) return fail(WEFQ_EUNSUPPORTED, "Kmax and Lmax must lie in [0, 16]");
+  if (n_beta < 0 || n_beta > WEFQ_MAX_BETA) return fail(WEFQ_EINVAL, "n_beta must lie in [0, WEFQ_MAX_BETA]");
+  if (n_beta > 0 && !beta) return fail(WEFQ_EINVAL, "null angular factor with n_beta > 0");
+  for (int j = 0; j < n_beta; ++j)
+    if (!std::isfinite(beta[j])) return fail(WEFQ_EINVAL, "non-finite angular factor coefficient");
   double gamma;
   switch (model) {
     case WEFQ_MAXWELL: gamma = 0.0; break;
@@ -409,6 +414,7 @@ static wefq_status new_core(int32_t model, double gamma_in, double b0, int32_t K
   h->gamma = gamma;
   h->b0 = b0 > 0 ? b0 : 1.0 / (4.0 * 3.141592653589793238462643383279502884);
   h->precisions = prec;
+  if (n_beta > 0) h->beta.assign(beta, beta + n_beta);
   h->chans = enumerate_channels(h->L);
   h->NT = (int)h->chans.size();
   coo = build_coo(h->L);
@@ -438,7 +444,7 @@ wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handl
     wefq_core* h = nullptr;
     std::vector<CooRow> coo;
     wefq_status st = new_core(desc->model, desc->gamma, desc->b0, desc->Kmax, desc->Lmax, desc->precisions,
-                              desc->device, &h, coo);
+                              desc->device, desc->n_beta, desc->beta, &h, coo);
     if (st != WEFQ_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if (!build_radial_core(h, coo, s)) { free_core(h); return WEFQ_EHIP; }
@@ -461,6 +467,8 @@ wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info) {
   info->flop_alg_per_cell = 2.0 * nk * nk * h->NG + 2.0 * nk * nk * nk * h->NS;
   info->gamma = h->gamma; info->b0 = h->b0;
   info->model = h->model;
+  info->n_beta = (int64_t)h->beta.size();
+  for (int j = 0; j < WEFQ_MAX_BETA; ++j) info->beta[j] = j < (int)h->beta.size() ? h->beta[j] : 0.0;
   return WEFQ_OK;
 }
 
@@ -473,9 +481,11 @@ wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count) {
 
 // ---- serialization: the raw radial core and its parameters
 //
-// File layout (native byte order): CoreFileHeader, then N_T * NK^3 doubles of the core
-// before the invariant-row zeroing, [c][k1][k2][k3] in the paper's channel order.  The
-// checksum is the 64-bit FNV-1a hash of the payload bytes.
+// File layout (native byte order): CoreFileHeader; for version 2 (a core with an angular
+// factor) a CoreFileAngular record; then N_T * NK^3 doubles of the core before the
+// invariant-row zeroing, [c][k1][k2][k3] in the paper's channel order.  An isotropic
+// core is written as version 1.  The checksum is the 64-bit FNV-1a hash of the payload
+// bytes.
 struct CoreFileHeader {
   char magic[8];
   uint32_t version, header_bytes;
@@ -483,6 +493,10 @@ struct CoreFileHeader {
   double gamma, b0;
   int64_t quad_nodes;
   uint64_t count, checksum;
+};
+struct CoreFileAngular {
+  int32_t n_beta, pad;
+  double beta[WEFQ_MAX_BETA];
 };
 static const char kCoreMagic[8] = {'W', 'E', 'F', 'Q', 'C', 'O', 'R', 'E'};
 
@@ -499,8 +513,13 @@ wefq_status wefq_core_save(wefq_handle h, const char* path) {
   CoreFileHeader hd;
   std::memset(&hd, 0, sizeof(hd));
   std::memcpy(hd.magic, kCoreMagic, 8);
-  hd.version = 1;
-  hd.header_bytes = sizeof(CoreFileHeader);
+  const bool angular = !h->beta.empty();
+  CoreFileAngular an;
+  std::memset(&an, 0, sizeof(an));
+  an.n_beta = (int32_t)h->beta.size();
+  for (size_t j = 0; j < h->beta.size(); ++j) an.beta[j] = h->beta[j];
+  hd.version = angular ? 2 : 1;
+  hd.header_bytes = sizeof(CoreFileHeader) + (angular ? sizeof(CoreFileAngular) : 0);
   hd.model = h->model; hd.K = h->K; hd.L = h->L; hd.NT = h->NT; hd.NK = h->NK;
   hd.gamma = h->gamma; hd.b0 = h->b0; hd.quad_nodes = h->quad_nodes;
   hd.count = h->R64raw.size();
@@ -508,6 +527,7 @@ wefq_status wefq_core_save(wefq_handle h, const char* path) {
   FILE* fp = std::fopen(path, "wb");
   if (!fp) return fail(WEFQ_EINVAL, std::string("cannot open for writing: ") + path);
   bool ok = std::fwrite(&hd, sizeof(hd), 1, fp) == 1 &&
+            (!angular || std::fwrite(&an, sizeof(an), 1, fp) == 1) &&
             std::fwrite(h->R64raw.data(), sizeof(double), h->R64raw.size(), fp) == h->R64raw.size();
   ok = (std::fclose(fp) == 0) && ok;
   if (!ok) return fail(WEFQ_EINVAL, std::string("write failed: ") + path);
@@ -521,11 +541,16 @@ wefq_status wefq_core_load(const char* path, uint32_t precisions, int32_t device
     FILE* fp = std::fopen(path, "rb");
     if (!fp) return fail(WEFQ_EINVAL, std::string("cannot open: ") + path);
     CoreFileHeader hd;
+    CoreFileAngular an;
+    std::memset(&an, 0, sizeof(an));
     std::vector<double> raw;
     bool ok = std::fread(&hd, sizeof(hd), 1, fp) == 1 && std::memcmp(hd.magic, kCoreMagic, 8) == 0 &&
-              hd.version == 1 && hd.header_bytes == sizeof(CoreFileHeader) && hd.K >= 0 && hd.K <= 16 &&
-              hd.L >= 0 && hd.L <= 16 && hd.NK == hd.K + 1 &&
+              (hd.version == 1 || hd.version == 2) &&
+              hd.header_bytes == sizeof(CoreFileHeader) + (hd.version == 2 ? sizeof(CoreFileAngular) : 0) &&
+              hd.K >= 0 && hd.K <= 16 && hd.L >= 0 && hd.L <= 16 && hd.NK == hd.K + 1 &&
               hd.count == (uint64_t)hd.NT * hd.NK * hd.NK * hd.NK && hd.NT > 0;
+    if (ok && hd.version == 2)
+      ok = std::fread(&an, sizeof(an), 1, fp) == 1 && an.n_beta >= 1 && an.n_beta <= WEFQ_MAX_BETA;
     if (ok) {
       raw.resize(hd.count);
       ok = std::fread(raw.data(), sizeof(double), raw.size(), fp) == raw.size() && std::fgetc(fp) == EOF &&
@@ -535,7 +560,7 @@ wefq_status wefq_core_load(const char* path, uint32_t precisions, int32_t device
     if (!ok) return fail(WEFQ_EINVAL, std::string("not a valid core file (header, size or checksum): ") + path);
     wefq_core* h = nullptr;
     std::vector<CooRow> coo;
-    wefq_status st = new_core(hd.model, hd.gamma, hd.b0, hd.K, hd.L, precisions, device, &h, coo);
+    wefq_status st = new_core(hd.model, hd.gamma, hd.b0, hd.K, hd.L, precisions, device, an.n_beta, an.beta, &h, coo);
     if (st != WEFQ_OK) return st;
     if (h->NT != hd.NT) { free_core(h); return fail(WEFQ_EINVAL, "channel count does not match the truncation"); }
     h->R64 = std::move(raw);

@@ -21,6 +21,16 @@
 // average of the test function (Funk-Hecke: it commutes with rotations), a 1-D
 // Gauss-Legendre integral.  All integrands are polynomials in (G^2, u^2, mu)
 // times the weights, so every rule is exact: the result carries only rounding.
+//
+// With an angular factor, B = b0 u^gamma beta(cos chi), cos chi = u_hat . n, the gain
+// sphere average A_klm(G, u_hat, r) = int dn beta(u_hat . n) phi_klm(G z + r n) is no
+// longer h_kl(G, r) Y_lm(G_hat): it is integrated directly at every node, with n measured
+// from u_hat (Gauss-Legendre in cos chi weighted by beta, trapezoid in the azimuth; exact
+// for a polynomial beta), for every cos-type (l, m >= 0) -- v, w and u_hat lie in the x-z
+// plane, so sin-type terms vanish by the y -> -y reflection.  The gain of a channel is
+// then sum_{m1,m2,m3 >= 0} g(l1 m1, l2 m2, l3 m3) A_{k1 l1 m1} S_l2m2(v) S_l3m3(w), and the
+// loss is scaled by int dn beta(u_hat . n) / (4 pi).  The outer rules are unchanged: A is
+// a polynomial of the same degree in (G, r) and of degree <= min(J, 2 k1 + l1) in u_hat.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -140,6 +150,91 @@ __global__ void core_nodes_kernel(NodeParams p) {
   if (l == 0) p.V2[i] = v2;
 }
 
+struct GainParams {
+  int P, K, L, NK, nt, ne;
+  const double* G;       // [P]
+  const double* u;       // [P]
+  const double* mu;      // [P]
+  const double* t;       // [nt] Gauss-Legendre nodes in cos chi
+  const double* wt;      // [nt] weight * beta(t) * 2pi / ne
+  const double* ce;      // [ne] cos of the azimuth nodes
+  const double* se;      // [ne] sin of the azimuth nodes
+  const double* Nkl;     // [L+1][NK]
+  const double* NlmR;    // [(L+1)(L+2)/2]
+  double* A;             // [(L+1)(L+2)/2][NK][P] gain averages A_klm
+};
+
+// 1/n for n = 1..17: the recurrences below divide only by these small integers.
+__constant__ double kRecip[18] = {0.0,       1.0,       1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,
+                                  1.0 / 6,   1.0 / 7,   1.0 / 8,  1.0 / 9,  1.0 / 10, 1.0 / 11,
+                                  1.0 / 12,  1.0 / 13,  1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17};
+
+// Thread per (node, l, m >= 0): the beta-weighted gain sphere average of phi_klm for all k.
+// Threads of a wavefront share (l, m) except at P boundaries, so the loops are uniform.
+__global__ __launch_bounds__(256) void core_gain_angular_kernel(GainParams p) {
+  const long P = p.P;
+  const int NLM = (p.L + 1) * (p.L + 2) / 2;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= P * NLM) return;
+  const int lm = (int)(tid / P);
+  const long i = tid % P;
+  int l = 0;
+  while ((l + 1) * (l + 2) / 2 <= lm) ++l;
+  const int m = lm - l * (l + 1) / 2;
+  const double G = p.G[i], r = 0.5 * p.u[i], mu = p.mu[i];
+  const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+  const double a = l + 0.5;
+  double dfac = 1.0;
+  for (int j = 1; j <= m; ++j) dfac *= (2 * j - 1);
+  double acc[17];
+#pragma unroll
+  for (int k = 0; k < 17; ++k) acc[k] = 0.0;
+  for (int it = 0; it < p.nt; ++it) {
+    const double t = p.t[it], sn = sqrt(fmax(0.0, 1.0 - t * t));
+    // n = t u_hat + sn (cos eps e1 + sin eps e2): u_hat = (st, 0, mu), e1 = (mu, 0, -st), e2 = y
+    const double bx = t * st, bz = t * mu, cx = sn * mu, cz = -sn * st;
+    for (int ie = 0; ie < p.ne; ++ie) {
+      const double ce = p.ce[ie], se = p.se[ie];
+      const double xx = r * (bx + cx * ce), xy = r * sn * se, xz = G + r * (bz + cz * ce);
+      const double x2 = xx * xx + xy * xy + xz * xz;
+      // cos-type solid harmonic: Re((x + i y)^m) Pi_lm(z, |x|^2)
+      double re = 1.0, im = 0.0;
+      for (int j = 0; j < m; ++j) {
+        const double nr = re * xx - im * xy;
+        im = re * xy + im * xx;
+        re = nr;
+      }
+      double pl = dfac;
+      if (l > m) {
+        double p0 = dfac, p1 = (2 * m + 1) * xz * dfac;
+        pl = p1;
+        for (int j = m + 2; j <= l; ++j) {
+          const double p2 = ((2 * j - 1) * xz * p1 - (j + m - 1) * x2 * p0) * kRecip[j - m];
+          p0 = p1; p1 = p2; pl = p2;
+        }
+      }
+      const double w = p.wt[it] * re * pl;
+      const double xh = 0.5 * x2;
+      double q0 = 1.0, q1 = 1.0 + a - xh;
+      acc[0] += w;
+      if (p.K >= 1) acc[1] += w * q1;
+#pragma unroll
+      for (int k = 1; k < 16; ++k) {
+        if (k < p.K) {
+          const double q2 = ((2 * k + 1 + a - xh) * q1 - (k + a) * q0) * kRecip[k + 1];
+          q0 = q1; q1 = q2;
+          acc[k + 1] += w * q1;
+        }
+      }
+    }
+  }
+  const double* nk = p.Nkl + (long)l * p.NK;
+  const double nlm = p.NlmR[lm];
+#pragma unroll
+  for (int k = 0; k < 17; ++k)
+    if (k <= p.K) p.A[((long)lm * p.NK + k) * P + i] = nlm * nk[k] * acc[k];
+}
+
 struct ChanParams {
   int P, NK, L;
   const double* W;       // [P] node weights
@@ -155,35 +250,60 @@ struct ChanParams {
   const double* gl;       // [NT]: 4pi Y_l1,0 Y_l2,0 Y_l3,0 (z) g(l1 0, l2 0, l3 0)
   const double* invS;     // [NT]
   double* R;              // [NT][NK^3]
+  const double* A;        // angular factor: gain averages [(L+1)(L+2)/2][NK][P]; null when isotropic
+  const int* eoff;        // [NT*17+1] ranges of the cos-type Gaunt entries per (channel, m1)
+  const int* emm;         // m2 | m3 << 8 (all m >= 0)
+  const double* eg;       // g(l1 m1, l2 m2, l3 m3)
 };
 
-constexpr int NODE_BLOCK = 32;
+constexpr int NODE_BLOCK = 64;
+constexpr int ROW = 18;                    // LDS row stride in doubles: 16-byte aligned rows
 
-// One workgroup per channel; thread t owns the (k1, k2) pair t and all k3.
-__global__ void core_accumulate_kernel(ChanParams p) {
+// One workgroup per channel; thread t owns the (k1, k2) pair t and all NK values of k3,
+// held in registers (NK is a template parameter so that the accumulators are not
+// indexed at run time).
+template <int NK>
+__global__ __launch_bounds__(320) void core_accumulate_kernel(ChanParams p) {
   const int c = blockIdx.x;
-  const int NK = p.NK;
   const int l1 = p.cl[3 * c], l2 = p.cl[3 * c + 1], l3 = p.cl[3 * c + 2];
   const long P = p.P;
-  __shared__ double sX[NODE_BLOCK][17];
-  __shared__ double sA[NODE_BLOCK][17];
-  __shared__ double sB[NODE_BLOCK][17];
+  __shared__ __align__(16) double sX[NODE_BLOCK][ROW];
+  __shared__ __align__(16) double sA[NODE_BLOCK][ROW];
+  __shared__ __align__(16) double sB[NODE_BLOCK][ROW];
   __shared__ double sig[NODE_BLOCK][2];
+  __shared__ double sS[NODE_BLOCK][17];     // per-node gain sums over m2, m3 for each m1
   const int t = threadIdx.x;
   const int k1 = t / NK, k2 = t % NK;
   const bool active = t < NK * NK;
-  double acc[17];
-  for (int k = 0; k < 17; ++k) acc[k] = 0.0;
+  double acc[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) acc[k] = 0.0;
   const int mmax = l2 < l3 ? l2 : l3;
   const int epow = (l1 + l2 - l3) / 2;
   for (long p0 = 0; p0 < P; p0 += NODE_BLOCK) {
     int nb = (int)((P - p0) < NODE_BLOCK ? (P - p0) : NODE_BLOCK);
+    if (p.A) {
+      // gain sums per (node, m1), spread over the whole workgroup
+      for (int w = t; w < nb * (l1 + 1); w += blockDim.x) {
+        const int j = w % nb, m1 = w / nb;
+        const long i = p0 + j;
+        double a = 0.0;
+        for (int e = p.eoff[c * 17 + m1]; e < p.eoff[c * 17 + m1 + 1]; ++e) {
+          const int mm = p.emm[e];
+          a += p.eg[e] * p.Sv[(long)(l2 * (l2 + 1) / 2 + (mm & 255)) * P + i] *
+               p.Sw[(long)(l3 * (l3 + 1) / 2 + (mm >> 8)) * P + i];
+        }
+        sS[j][m1] = a * p.W[i];
+      }
+    }
     if (t < nb) {
       long i = p0 + t;
       double sg = 0.0;
-      for (int m = 0; m <= mmax; ++m)
-        sg += p.gz[(long)c * (p.L + 1) + m] * p.Sv[(long)(l2 * (l2 + 1) / 2 + m) * P + i] *
-              p.Sw[(long)(l3 * (l3 + 1) / 2 + m) * P + i];
+      if (!p.A) {
+        for (int m = 0; m <= mmax; ++m)
+          sg += p.gz[(long)c * (p.L + 1) + m] * p.Sv[(long)(l2 * (l2 + 1) / 2 + m) * P + i] *
+                p.Sw[(long)(l3 * (l3 + 1) / 2 + m) * P + i];
+      }
       double vp = 1.0, v2 = p.V2[i];
       for (int e = 0; e < epow; ++e) vp *= v2;
       double sl = p.gl[c] * p.Bi[(long)l3 * P + i] * vp;
@@ -194,23 +314,46 @@ __global__ void core_accumulate_kernel(ChanParams p) {
     for (int e = t; e < nb * NK; e += blockDim.x) {
       int j = e / NK, k = e % NK;
       long i = p0 + j;
-      sX[j][k] = sig[j][0] * p.Hg[((long)l1 * NK + k) * P + i] - sig[j][1] * p.Pv[((long)l1 * NK + k) * P + i];
+      double gain;
+      if (p.A) {
+        gain = 0.0;
+        for (int m1 = 0; m1 <= l1; ++m1)
+          gain += sS[j][m1] * p.A[((long)(l1 * (l1 + 1) / 2 + m1) * NK + k) * P + i];
+      } else {
+        gain = sig[j][0] * p.Hg[((long)l1 * NK + k) * P + i];
+      }
+      sX[j][k] = gain - sig[j][1] * p.Pv[((long)l1 * NK + k) * P + i];
       sA[j][k] = p.Pv[((long)l2 * NK + k) * P + i];
       sB[j][k] = p.Pw[((long)l3 * NK + k) * P + i];
     }
     __syncthreads();
     if (active) {
       for (int j = 0; j < nb; ++j) {
-        double xa = sX[j][k1] * sA[j][k2];
+        const double xa = sX[j][k1] * sA[j][k2];
+#pragma unroll
         for (int k3 = 0; k3 < NK; ++k3) acc[k3] += xa * sB[j][k3];
       }
     }
     __syncthreads();
   }
   if (active) {
-    double s = p.invS[c];
+    const double s = p.invS[c];
+#pragma unroll
     for (int k3 = 0; k3 < NK; ++k3)
       p.R[(long)c * NK * NK * NK + ((long)k1 * NK + k2) * NK + k3] = acc[k3] * s;
+  }
+}
+
+static void launch_accumulate(int NK, int NT, hipStream_t stream, const ChanParams& cp) {
+  const dim3 grid(NT), block(((NK * NK + 63) / 64) * 64);
+  switch (NK) {
+#define WEFQ_ACC_CASE(n) \
+    case n: hipLaunchKernelGGL(core_accumulate_kernel<n>, grid, block, 0, stream, cp); break;
+    WEFQ_ACC_CASE(1) WEFQ_ACC_CASE(2) WEFQ_ACC_CASE(3) WEFQ_ACC_CASE(4) WEFQ_ACC_CASE(5) WEFQ_ACC_CASE(6)
+    WEFQ_ACC_CASE(7) WEFQ_ACC_CASE(8) WEFQ_ACC_CASE(9) WEFQ_ACC_CASE(10) WEFQ_ACC_CASE(11) WEFQ_ACC_CASE(12)
+    WEFQ_ACC_CASE(13) WEFQ_ACC_CASE(14) WEFQ_ACC_CASE(15) WEFQ_ACC_CASE(16) WEFQ_ACC_CASE(17)
+#undef WEFQ_ACC_CASE
+    default: break;
   }
 }
 
@@ -236,6 +379,34 @@ bool build_radial_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t
   gauss_rule(0, nnu, 0.0, xn, wn);
   const long P = (long)nsig * nsig * nmu;
   h->quad_nodes = P;
+  // angular factor: beta-weighted Gauss-Legendre rule in cos chi (exact to degree D + J,
+  // the degree of phi(G + r n) in n plus that of beta) and a trapezoid rule of D + 1
+  // azimuths (exact for trigonometric degree D)
+  const bool angular = !h->beta.empty();
+  const int J = angular ? (int)h->beta.size() - 1 : 0;
+  const int nt = angular ? (D + J) / 2 + 1 : 0, ne = angular ? D + 1 : 0;
+  std::vector<double> tt, wt, ce, se;
+  double loss_scale = 1.0;                           // int dn beta(u_hat . n) / (4 pi)
+  if (angular) {
+    const double pi_ = 3.141592653589793238462643383279502884;
+    std::vector<double> w_t;
+    gauss_rule(0, nt, 0.0, tt, w_t);
+    wt.resize(nt);
+    double bint = 0.0;
+    for (int a = 0; a < nt; ++a) {
+      double p0 = 1.0, p1 = tt[a], b = h->beta[0];
+      for (int j = 1; j <= J; ++j) {
+        b += h->beta[j] * p1;
+        const double p2 = ((2 * j + 1) * tt[a] * p1 - j * p0) / (j + 1);
+        p0 = p1; p1 = p2;
+      }
+      wt[a] = w_t[a] * b * 2 * pi_ / ne;
+      bint += w_t[a] * b;
+    }
+    loss_scale = 2 * pi_ * bint / (4 * pi_);
+    ce.resize(ne); se.resize(ne);
+    for (int j = 0; j < ne; ++j) { ce[j] = std::cos(2 * pi_ * j / ne); se[j] = std::sin(2 * pi_ * j / ne); }
+  }
   const double pi = 3.141592653589793238462643383279502884;
   const double pref = h->b0 * std::pow(2 * pi, -3.0) * 8 * pi * pi * 0.5 * std::pow(2.0, 2.0 + h->gamma);
   std::vector<double> G(P), U(P), MU(P), W(P);
@@ -271,10 +442,27 @@ bool build_radial_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t
     double y3 = std::sqrt((2 * ch.l3 + 1) / (4 * pi));
     for (int m = 0; m <= std::min(ch.l2, ch.l3); ++m)
       gz[(size_t)c * (L + 1) + m] = y1 * real_gaunt(ch.l1, 0, ch.l2, m, ch.l3, m);
-    gl[c] = 4 * pi * y1 * y2 * y3 * real_gaunt(ch.l1, 0, ch.l2, 0, ch.l3, 0);
+    gl[c] = 4 * pi * loss_scale * y1 * y2 * y3 * real_gaunt(ch.l1, 0, ch.l2, 0, ch.l3, 0);
     invS[c] = invS[c] > 0 ? 1.0 / invS[c] : 0.0;
   }
   const int NLM = (L + 1) * (L + 2) / 2;
+  // cos-type Gaunt entries for the angular gain, grouped by (channel, m1): the COO rows with
+  // m1, m2, m3 >= 0
+  std::vector<int> eoff((size_t)NT * 17 + 1, 0), emm;
+  std::vector<double> eg;
+  if (angular) {
+    std::vector<std::vector<std::pair<int, double>>> per((size_t)NT * 17);
+    for (const CooRow& r : coo) {
+      const int l1 = l_of_q(r.q1), l2 = l_of_q(r.q2), l3 = l_of_q(r.q3);
+      const int m1 = r.q1 - l1 * l1 - l1, m2 = r.q2 - l2 * l2 - l2, m3 = r.q3 - l3 * l3 - l3;
+      if (m1 < 0 || m2 < 0 || m3 < 0) continue;
+      per[(size_t)r.c * 17 + m1].push_back({m2 | (m3 << 8), r.g});
+    }
+    for (size_t b = 0; b < per.size(); ++b) {
+      eoff[b + 1] = eoff[b] + (int)per[b].size();
+      for (auto& e : per[b]) { emm.push_back(e.first); eg.push_back(e.second); }
+    }
+  }
   // device buffers (temporary)
   std::vector<void*> tmp;
   auto dalloc = [&](size_t bytes) -> double* {
@@ -293,6 +481,15 @@ bool build_radial_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t
   double *dgz = dalloc(gz.size() * 8), *dgl = dalloc(NT * 8), *dinvS = dalloc(NT * 8);
   int* dcl = (int*)dalloc(cl.size() * sizeof(int));
   double* dR = dalloc((size_t)NT * NK * NK * NK * 8);
+  double *dA = nullptr, *dtt = nullptr, *dwt = nullptr, *dce = nullptr, *dse = nullptr, *deg = nullptr;
+  int *deoff = nullptr, *demm = nullptr;
+  if (angular) {
+    dA = dalloc((size_t)NLM * NK * P * 8);
+    dtt = dalloc(nt * 8); dwt = dalloc(nt * 8); dce = dalloc(ne * 8); dse = dalloc(ne * 8);
+    deoff = (int*)dalloc(eoff.size() * sizeof(int));
+    demm = (int*)dalloc(std::max<size_t>(1, emm.size()) * sizeof(int));
+    deg = dalloc(std::max<size_t>(1, eg.size()) * 8);
+  }
   for (void* p : tmp)
     if (!p) { cleanup(); set_error("device allocation failed in core build"); return false; }
   bool ok = true;
@@ -304,15 +501,27 @@ bool build_radial_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t
   up(dNkl, Nkl.data(), Nkl.size() * 8); up(dNlm, NlmR.data(), NlmR.size() * 8);
   up(dgz, gz.data(), gz.size() * 8); up(dgl, gl.data(), NT * 8); up(dinvS, invS.data(), NT * 8);
   up(dcl, cl.data(), cl.size() * sizeof(int));
+  if (angular) {
+    up(dtt, tt.data(), nt * 8); up(dwt, wt.data(), nt * 8); up(dce, ce.data(), ne * 8); up(dse, se.data(), ne * 8);
+    up(deoff, eoff.data(), eoff.size() * sizeof(int));
+    if (!emm.empty()) { up(demm, emm.data(), emm.size() * sizeof(int)); up(deg, eg.data(), eg.size() * 8); }
+  }
   if (!ok) { cleanup(); set_error("upload failed in core build"); return false; }
   NodeParams np{(int)P, K, L, NK, nnu, dG, dU, dMU, dnu, dwnu, dNkl, dNlm, dPv, dPw, dHg, dSv, dSw, dBi, dV2};
   long threads = P * (L + 1);
   hipLaunchKernelGGL(core_nodes_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, np);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) { cleanup(); set_error(std::string("core node kernel: ") + hipGetErrorString(e)); return false; }
-  ChanParams cp{(int)P, NK, L, dW, dPv, dPw, dHg, dSv, dSw, dBi, dV2, dcl, dgz, dgl, dinvS, dR};
-  int bs = ((NK * NK + 63) / 64) * 64;
-  hipLaunchKernelGGL(core_accumulate_kernel, dim3(NT), dim3(bs), 0, stream, cp);
+  if (angular) {
+    GainParams gp{(int)P, K, L, NK, nt, ne, dG, dU, dMU, dtt, dwt, dce, dse, dNkl, dNlm, dA};
+    const long gthreads = P * NLM;
+    hipLaunchKernelGGL(core_gain_angular_kernel, dim3((unsigned)((gthreads + 255) / 256)), dim3(256), 0, stream, gp);
+    e = hipGetLastError();
+    if (e != hipSuccess) { cleanup(); set_error(std::string("core gain kernel: ") + hipGetErrorString(e)); return false; }
+  }
+  ChanParams cp{(int)P, NK, L, dW, dPv, dPw, dHg, dSv, dSw, dBi, dV2, dcl, dgz, dgl, dinvS, dR,
+                dA, deoff, demm, deg};
+  launch_accumulate(NK, NT, stream, cp);
   e = hipGetLastError();
   if (e != hipSuccess) { cleanup(); set_error(std::string("core accumulate kernel: ") + hipGetErrorString(e)); return false; }
   h->R64.assign((size_t)NT * NK * NK * NK, 0.0);

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <complex>
 #include <stdexcept>
+#include <thread>
 
 #include "wefq_host.h"
 
@@ -18,12 +19,12 @@ std::vector<Channel> enumerate_channels(int L) {
 }
 
 static long double lfact(int n) {
-  static std::vector<long double> tab;
-  if (tab.empty()) {
-    tab.resize(200);
-    tab[0] = 1.0L;
-    for (int i = 1; i < 200; ++i) tab[i] = tab[i - 1] * (long double)i;
-  }
+  static const std::vector<long double> tab = [] {   // thread-safe one-time initialization
+    std::vector<long double> t(200);
+    t[0] = 1.0L;
+    for (int i = 1; i < 200; ++i) t[i] = t[i - 1] * (long double)i;
+    return t;
+  }();
   if (n < 0 || n >= 200) throw std::runtime_error("factorial argument out of range");
   return tab[n];
 }
@@ -64,12 +65,9 @@ static int real_to_complex(int m, std::pair<int, std::complex<long double>> out[
   return 2;
 }
 
-double real_gaunt(int l1, int m1, int l2, int m2, int l3, int m3) {
-  if ((l1 + l2 + l3) & 1) return 0.0;
-  if (l3 < std::abs(l1 - l2) || l3 > l1 + l2) return 0.0;
-  const long double pi = 3.141592653589793238462643383279502884L;
-  long double base = std::sqrt((long double)(2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1) / (4.0L * pi)) *
-                     wigner3j(l1, l2, l3, 0, 0, 0);
+// The real Gaunt weight given the m-independent factor
+// base = sqrt((2l1+1)(2l2+1)(2l3+1)/(4 pi)) (l1 l2 l3; 0 0 0).
+static double real_gaunt_base(long double base, int l1, int m1, int l2, int m2, int l3, int m3) {
   std::pair<int, std::complex<long double>> a[2], b[2], c[2];
   int na = real_to_complex(m1, a), nb = real_to_complex(m2, b), nc = real_to_complex(m3, c);
   std::complex<long double> acc = 0.0L;
@@ -83,28 +81,66 @@ double real_gaunt(int l1, int m1, int l2, int m2, int l3, int m3) {
   return (double)(acc.real() * base);
 }
 
-std::vector<CooRow> build_coo(int L, double tol) {
-  std::vector<Channel> ch = enumerate_channels(L);
-  int NQ = (L + 1) * (L + 1);
-  std::vector<int> cid((L + 1) * (L + 1) * (L + 1), -1);
-  for (size_t i = 0; i < ch.size(); ++i) cid[(ch[i].l1 * (L + 1) + ch[i].l2) * (L + 1) + ch[i].l3] = (int)i;
-  std::vector<CooRow> rows;
-  for (int q3 = 0; q3 < NQ; ++q3) {
-    int l3 = l_of_q(q3), m3 = q3 - l3 * l3 - l3;
+static long double gaunt_base(int l1, int l2, int l3) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  return std::sqrt((long double)(2 * l1 + 1) * (2 * l2 + 1) * (2 * l3 + 1) / (4.0L * pi)) *
+         wigner3j(l1, l2, l3, 0, 0, 0);
+}
+
+double real_gaunt(int l1, int m1, int l2, int m2, int l3, int m3) {
+  if ((l1 + l2 + l3) & 1) return 0.0;
+  if (l3 < std::abs(l1 - l2) || l3 > l1 + l2) return 0.0;
+  return real_gaunt_base(gaunt_base(l1, l2, l3), l1, m1, l2, m2, l3, m3);
+}
+
+// Rows for q3 in [q3a, q3b), in table order.  For given (q2, q3) only the channels'
+// l1 (triangle rule, even sum) and |m1| in {|m2| + |m3|, ||m2| - |m3||} can carry a
+// nonzero weight (the complex components need mu1 + mu2 + mu3 = 0), so only those q1 are
+// visited, in increasing order.
+static void coo_rows(int L, double tol, const std::vector<int>& cid, const std::vector<long double>& base, int q3a,
+                     int q3b, std::vector<CooRow>& rows) {
+  const int NQ = (L + 1) * (L + 1);
+  for (int q3 = q3a; q3 < q3b; ++q3) {
+    const int l3 = l_of_q(q3), m3 = q3 - l3 * l3 - l3;
     for (int q2 = 0; q2 < NQ; ++q2) {
-      int l2 = l_of_q(q2), m2 = q2 - l2 * l2 - l2;
-      for (int q1 = 0; q1 < NQ; ++q1) {
-        int l1 = l_of_q(q1), m1 = q1 - l1 * l1 - l1;
-        int c = cid[(l1 * (L + 1) + l2) * (L + 1) + l3];
+      const int l2 = l_of_q(q2), m2 = q2 - l2 * l2 - l2;
+      const int a2 = std::abs(m2), a3 = std::abs(m3);
+      for (int l1 = std::abs(l2 - l3); l1 <= std::min(L, l2 + l3); l1 += 2) {
+        const int ci = (l1 * (L + 1) + l2) * (L + 1) + l3;
+        const int c = cid[ci];
         if (c < 0) continue;
-        // complex components need mu1+mu2+mu3 = 0 with |mu_i| = |m_i|
-        int a1 = std::abs(m1), a2 = std::abs(m2), a3 = std::abs(m3);
-        if (a1 != a2 + a3 && a1 != std::abs(a2 - a3)) continue;
-        double g = real_gaunt(l1, m1, l2, m2, l3, m3);
-        if (std::fabs(g) > tol) rows.push_back({q1, q2, q3, c, g});
+        int cand[4] = {-(a2 + a3), -std::abs(a2 - a3), std::abs(a2 - a3), a2 + a3};
+        for (int i = 0; i < 4; ++i) {
+          const int m1 = cand[i];
+          if (i > 0 && m1 == cand[i - 1]) continue;
+          if (std::abs(m1) > l1) continue;
+          double g = real_gaunt_base(base[ci], l1, m1, l2, m2, l3, m3);
+          if (std::fabs(g) > tol) rows.push_back({l1 * l1 + l1 + m1, q2, q3, c, g});
+        }
       }
     }
   }
+}
+
+std::vector<CooRow> build_coo(int L, double tol) {
+  std::vector<Channel> ch = enumerate_channels(L);
+  const int NQ = (L + 1) * (L + 1);
+  std::vector<int> cid((L + 1) * (L + 1) * (L + 1), -1);
+  std::vector<long double> base(cid.size(), 0.0L);
+  for (size_t i = 0; i < ch.size(); ++i) {
+    const int ci = (ch[i].l1 * (L + 1) + ch[i].l2) * (L + 1) + ch[i].l3;
+    cid[ci] = (int)i;
+    base[ci] = gaunt_base(ch[i].l1, ch[i].l2, ch[i].l3);
+  }
+  // q3 ranges on host threads; the pieces are concatenated in q3 order
+  const int nth = std::max(1, std::min({16, NQ, (int)std::thread::hardware_concurrency()}));
+  std::vector<std::vector<CooRow>> part(nth);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nth; ++t)
+    pool.emplace_back([&, t] { coo_rows(L, tol, cid, base, NQ * t / nth, NQ * (t + 1) / nth, part[t]); });
+  for (auto& th : pool) th.join();
+  std::vector<CooRow> rows;
+  for (auto& p : part) rows.insert(rows.end(), p.begin(), p.end());
   return rows;
 }
 

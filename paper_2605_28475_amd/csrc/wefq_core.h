@@ -16,6 +16,7 @@ struct wefq_core {
   int NT = 0, NG = 0, NS = 0;          // paper counts
   int NTm = 0, NGm = 0, NSm = 0;       // merged counts
   double gamma = 0.0, b0 = 0.0;
+  std::vector<double> beta;            // Legendre coefficients of the angular factor; empty: isotropic
   unsigned precisions = 0;
   int64_t quad_nodes = 0;
   int64_t device_bytes = 0;

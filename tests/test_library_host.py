@@ -73,6 +73,16 @@ def test_error_paths_without_device():
     assert b"[0, 16]" in lib.wefq_last_error()
     desc = _lib.CoreDesc(9, 0.0, 0.0, 4, 4, 0, 0)
     assert lib.wefq_build_core(ctypes.byref(desc), None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    # angular factor: too many coefficients, a null array, a non-finite coefficient
+    coef = (ctypes.c_double * 40)(*([1.0] * 40))
+    ptr = ctypes.cast(coef, ctypes.POINTER(ctypes.c_double))
+    for n_beta, p in ((_lib.MAX_BETA + 1, ptr), (-1, ptr), (3, None)):
+        desc = _lib.CoreDesc(0, 0.0, 0.0, 4, 4, 0, 0, n_beta, p)
+        assert lib.wefq_build_core(ctypes.byref(desc), None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    coef[1] = float("nan")
+    desc = _lib.CoreDesc(0, 0.0, 0.0, 4, 4, 0, 0, 3, ptr)
+    assert lib.wefq_build_core(ctypes.byref(desc), None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    assert b"non-finite" in lib.wefq_last_error()
     assert lib.wefq_apply_Q(None, 1, None, None, 1, 1, 1, None) == _lib.WEFQ_EINVAL
     assert lib.wefq_destroy(None) == _lib.WEFQ_EINVAL
     n = ctypes.c_int64()
