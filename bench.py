@@ -102,12 +102,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16x3 comparison legs")
-    ap.add_argument("--workload", choices=["k12", "uneven", "serve", "rk", "jvp", "build"], default="k12",
+    ap.add_argument("--workload", choices=["k12", "uneven", "serve", "rk", "jvp", "build", "orderings"],
+                    default="k12",
                     help="k12: the headline batch; uneven: one persistent launch over a mix of cores; "
                          "serve: continuous-batching server under Poisson arrivals; "
                          "rk: batched RK4 time stepping (anisotropic stress relaxation, hard spheres); "
                          "jvp: Jacobian-vector products J(c) d on the headline batch; "
-                         "build: radial core build times, isotropic and with angular factors, and reload")
+                         "build: radial core build times, isotropic and with angular factors, and reload; "
+                         "orderings: naive, radial-first and angular-first FP64 at K = 4, L = 2..13")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of f (known byte count) for counter scaling")
     args = ap.parse_args()
@@ -131,6 +133,8 @@ def main():
         return bench_jvp(args, torch, wefq, synth)
     if args.workload == "build":
         return bench_build(args, torch, wefq)
+    if args.workload == "orderings":
+        return bench_orderings(args, torch, wefq, synth)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -267,6 +271,61 @@ def bench_build(args, torch, wefq):
     out = {"metric": "radial core build time, hard spheres, K = L = 12 (FP64 on the GPU)",
            "value": k12["build_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
            "dtype": "f64", "data": "synthetic", "config": {"workload": "core_build_hs"}, "builds": rows}
+    print(json.dumps(out), flush=True)
+
+
+def bench_orderings(args, torch, wefq, synth):
+    """The orderings of the factorized sum (Section 4.5) on one GPU, FP64, hard spheres,
+    K = 4 and L = 2..13, 16,384 cells: naive (every table row contracts its NK^3 block; on
+    2,048 cells), radial-first (the dense intermediate Psi through HBM, then one pass over the
+    table) and angular-first (the tiled MFMA kernel).  The dense Cartesian contraction is not
+    run; its count, 2 N^3 FLOPs per cell, is given for reference."""
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    K, B, nb_naive = 4, 16384, 2048
+    rows = []
+    for L in (2, 4, 6, 8, 10, 12, 13):
+        log(f"[orderings] K={K} L={L}")
+        core = wefq.Core("hs", K, L, device=0, precisions=("fp64", "radial"))
+        info = core.info
+        N, NK = core.N, K + 1
+        f = torch.tensor(synth.perturbed_maxwellian(K, L, B, seed=synth.BASE_SEED + 17), device=dev)
+        q = torch.empty_like(f)
+        core.apply_Q(f, out=q, precision="fp64")
+        ms_a, _ = time_steps(lambda: core.apply_Q(f, out=q, precision="fp64"), 10, stream, torch)
+        per64 = core.radial_workspace_bytes(64)
+        chunk = max(64, min(B, (1 << 30) // per64 * 64))
+        work = torch.empty(core.radial_workspace_bytes(chunk), dtype=torch.uint8, device=dev)
+        qr = torch.empty_like(f)
+        core.apply_Q_radial(f, out=qr, work=work)
+        ms_r, _ = time_steps(lambda: core.apply_Q_radial(f, out=qr, work=work), 3, stream, torch)
+        fn, qn = f[:nb_naive], torch.empty_like(f[:nb_naive])
+        core.apply_Q(fn, out=qn, precision="fp64_naive")
+        ms_n, _ = time_steps(lambda: core.apply_Q(fn, out=qn, precision="fp64_naive"), 2, stream, torch)
+        scale = q.abs().max().item()
+        err_r = (qr - q).abs().max().item() / scale
+        err_n = (qn - q[:nb_naive]).abs().max().item() / scale
+        t_a, t_r, t_n = (float(np.mean(m)) * 1e-3 for m in (ms_a, ms_r, ms_n))
+        groups = info["radial_groups"]
+        psi_bytes = 2.0 * groups * NK * 8 + 2.0 * N * 8          # Psi and the transposed f, written and read
+        rows.append({"L": L, "N": N, "N_G": info["N_G"], "N_S": info["N_S"], "radial_groups": groups,
+                     "angular_first_cells_per_s": B / t_a, "radial_first_cells_per_s": B / t_r,
+                     "naive_cells_per_s": nb_naive / t_n,
+                     "angular_vs_naive": (B / t_a) / (nb_naive / t_n), "angular_vs_radial": t_r / t_a,
+                     "radial_vs_naive": (B / t_r) / (nb_naive / t_n),
+                     "flop_per_cell": {"angular_first": info["flop_alg_per_cell"],
+                                       "radial_first": 2.0 * groups * (NK ** 3 + NK ** 2) + 2.0 * NK * info["N_G"],
+                                       "naive": 2.0 * NK ** 3 * info["N_G"], "dense": 2.0 * N ** 3},
+                     "radial_first_hbm_gb_s": psi_bytes * B / t_r / 1e9, "radial_chunk_cells": chunk,
+                     "rel_err_vs_angular": {"radial_first": err_r, "naive": err_n}})
+        del f, q, qr, work, fn, qn
+        core.close()
+    last = rows[-1]
+    out = {"metric": "FP64 Q(f,f) cell-evals/sec by ordering, hard spheres, K = 4, L = 13",
+           "value": last["angular_first_cells_per_s"], "unit": "cells/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic", "config": {"workload": f"orderings_hs_K{K}_L2-13_B{B}", "cells": B},
+           "orderings": rows}
     print(json.dumps(out), flush=True)
 
 

@@ -56,9 +56,11 @@ typedef enum {
   WEFQ_FP64_NAIVE = 8,    /* the paper's naive ordering of the factorized sum (Section 4.5.2):
                              every COO row contracts its full K^3 block, FP64, one thread per
                              output; a reference ordering, memory-bound on R; double */
-  WEFQ_PREP_BILINEAR = 16 /* not a precision: in wefq_core_desc.precisions, also prepare the
+  WEFQ_PREP_BILINEAR = 16,/* not a precision: in wefq_core_desc.precisions, also prepare the
                              tables of the non-symmetric bilinear form (wefq_apply_Qfg) for the
                              FP64 / FP32 precisions requested */
+  WEFQ_PREP_RADIAL = 32   /* not a precision: also prepare the tables of the radial-first
+                             ordering (wefq_apply_Q_radial); implies WEFQ_FP64 */
 } wefq_precision;
 
 /* Most Legendre coefficients of an angular factor (degree <= 32). */
@@ -99,6 +101,8 @@ typedef struct {
   int64_t model;          /* wefq_model of the core */
   int64_t n_beta;         /* angular factor: Legendre coefficients beta[0 .. n_beta) */
   double beta[WEFQ_MAX_BETA];
+  int64_t radial_groups;  /* distinct (channel, q2, q3) triples of the table when the
+                             radial-first tables are prepared, else 0 */
 } wefq_core_info;
 
 /* Build the radial core R (Sections 3.2-3.3, 4.3-4.4) on the GPU in FP64 and the
@@ -139,6 +143,27 @@ wefq_status wefq_core_load(const char* path, uint32_t precisions, int32_t device
  * exactly 0 for every precision.  NaN/Inf in f propagate elsewhere. */
 wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* Q,
                          int64_t B, int64_t ld_f, int64_t ld_q, void* stream);
+
+/* Workspace of wefq_apply_Q_radial for chunks of `chunk` cells (rounded up to a multiple
+ * of 64): chunk * (N + radial_groups * NK) * 8 bytes.  EINVAL if the core was built without
+ * WEFQ_PREP_RADIAL or chunk < 1. */
+wefq_status wefq_radial_workspace(wefq_handle h, int64_t chunk, int64_t* bytes);
+
+/* Q = Q(f, f) in FP64 by the radial-first ordering of the factorized sum (Section 4.5.3): for
+ * every distinct (channel c, q2, q3) of the table the dense intermediate
+ *   Psi^{k1}_{q2 q3 c} = sum_{k2, k3} R^{(c)}_{k1 k2 k3} f_{k2 q2} f_{k3 q3}
+ * is written to the workspace, then one pass over the table grouped by output state forms
+ * Q_{k1 q1} = sum_z g_z Psi^{k1}_{q2z q3z c_z}.  A reference ordering for comparison with
+ * wefq_apply_Q (the angular-first ordering); the results agree to FP64 rounding.
+ * f, Q: device pointers to double, row-major [B][ld], ld >= N, not overlapping each other or
+ * the workspace.  work: caller-owned device memory, 256-byte aligned, of work_bytes bytes;
+ * the batch runs in chunks of the largest multiple of 64 cells whose workspace
+ * (wefq_radial_workspace) fits work_bytes, at most 65,536.  Concurrent calls need separate
+ * workspaces.  The invariant rows of Q are exactly 0.  Needs a core built with
+ * WEFQ_PREP_RADIAL.  EINVAL for bad pointers or sizes, or a workspace smaller than one
+ * 64-cell chunk.  Asynchronous on stream; allocates nothing.  B == 0 is a no-op. */
+wefq_status wefq_apply_Q_radial(wefq_handle h, const double* f, double* Q, int64_t B, int64_t ld_f,
+                                int64_t ld_q, void* work, int64_t work_bytes, void* stream);
 
 /* Jacobian-vector product out = J(c) d = Q(c, d) + Q(d, c), the derivative of Q(f, f)
  * at f = c in the direction d, where Q(f, g) = sum C_{a1 a2 a3} f_a2 g_a3 is the

@@ -16,7 +16,7 @@ from ._lib import (BF16X3, FP32, FP64, FP64_NAIVE, HARD_SPHERE, MAXWELL, RK_CLAS
 
 MODELS = {"maxwell": MAXWELL, "mm": MAXWELL, "hard_sphere": HARD_SPHERE, "hs": HARD_SPHERE, "vhs": VHS}
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp64_naive": FP64_NAIVE,
-              "bilinear": _lib.PREP_BILINEAR}
+              "bilinear": _lib.PREP_BILINEAR, "radial": _lib.PREP_RADIAL}
 RK_SCHEMES = {"euler": RK_EULER, "heun": RK_HEUN, "ssp3": RK_SSP3, "rk4": RK_CLASSIC4}
 
 
@@ -116,6 +116,33 @@ class Core:
                                            out.stride(0) if B > 1 else out.shape[1],
                                            _stream_ptr(stream, f2.device)))
         return out[0] if squeeze else out
+
+    def radial_workspace_bytes(self, chunk):
+        """Workspace bytes of apply_Q_radial for chunks of `chunk` cells (wefq_radial_workspace)."""
+        n = ctypes.c_int64()
+        _lib.check(_lib.lib().wefq_radial_workspace(self._h, int(chunk), ctypes.byref(n)))
+        return n.value
+
+    def apply_Q_radial(self, f, out=None, work=None, chunk=None, stream=None):
+        """Q(f, f) in FP64 by the radial-first ordering (wefq_apply_Q_radial; core built with
+        "radial").  work: a uint8 device tensor; by default one is allocated for chunks of
+        `chunk` cells (default: the batch, capped so that the workspace stays under 1 GiB)."""
+        import torch
+        if f.dtype != torch.float64 or f.device.type != "cuda" or f.dim() != 2 or f.stride(-1) != 1:
+            raise ValueError("f must be a CUDA float64 [B, N] tensor with unit stride in the last dimension")
+        B = f.shape[0]
+        if out is None:
+            out = torch.empty((B, f.shape[1]), dtype=torch.float64, device=f.device)
+        if work is None:
+            per64 = self.radial_workspace_bytes(64)
+            if chunk is None:
+                chunk = max(64, min(((B + 63) // 64) * 64, (1 << 30) // per64 * 64))
+            work = torch.empty(self.radial_workspace_bytes(chunk), dtype=torch.uint8, device=f.device)
+        _lib.check(_lib.lib().wefq_apply_Q_radial(self._h, ctypes.c_void_p(f.data_ptr()),
+                                                  ctypes.c_void_p(out.data_ptr()), B, f.stride(0), out.stride(0),
+                                                  ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                                  _stream_ptr(stream, f.device)))
+        return out
 
     def apply_J(self, c, d, out=None, precision=None, stream=None):
         """Jacobian-vector product J(c) d = Q(c, d) + Q(d, c) for [B, N] device tensors."""

@@ -6,7 +6,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwefq.so"
 
 WEFQ_OK, WEFQ_EINVAL, WEFQ_ENOMEM, WEFQ_EHIP, WEFQ_EUNSUPPORTED, WEFQ_EBUDGET = range(6)
 MAXWELL, HARD_SPHERE, VHS = 0, 1, 2
-FP64, FP32, BF16X3, FP64_NAIVE, PREP_BILINEAR = 1, 2, 4, 8, 16
+FP64, FP32, BF16X3, FP64_NAIVE, PREP_BILINEAR, PREP_RADIAL = 1, 2, 4, 8, 16, 32
 RK_EULER, RK_HEUN, RK_SSP3, RK_CLASSIC4 = 1, 2, 3, 4
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED", 5: "EBUDGET"}
@@ -29,7 +29,8 @@ class CoreInfo(ctypes.Structure):
                 ("N_S_merged", ctypes.c_int64), ("quad_nodes", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("flop_alg_per_cell", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("b0", ctypes.c_double), ("model", ctypes.c_int64),
-                ("n_beta", ctypes.c_int64), ("beta", ctypes.c_double * MAX_BETA)]
+                ("n_beta", ctypes.c_int64), ("beta", ctypes.c_double * MAX_BETA),
+                ("radial_groups", ctypes.c_int64)]
 
 
 class Segment(ctypes.Structure):
@@ -56,6 +57,10 @@ _SIGNATURES = [
                                       ctypes.POINTER(ctypes.c_void_p)]),
     ("wefq_apply_Q", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]),
+    ("wefq_radial_workspace", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    ("wefq_apply_Q_radial", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p]),
     ("wefq_apply_J", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                     ctypes.c_void_p]),

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/wefq.h"
@@ -82,6 +83,32 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   if (!upload(h, h->dR64, h->R64, s) || !upload(h, h->d_q1ptr, q1ptr, s) || !upload(h, h->d_ent_c, ec, s) ||
       !upload(h, h->d_ent_q, eq, s) || !upload(h, h->d_ent_g, eg, s))
     return false;
+  // ---- radial-first ordering: distinct (channel, q2, q3) groups in table order, and the
+  // rows grouped by q1 (the order above) pointing at their group
+  if (h->precisions & WEFQ_PREP_RADIAL) {
+    std::unordered_map<int64_t, int> gid;
+    gid.reserve(coo.size());
+    std::vector<int> grp_c, row_grp(coo.size());
+    std::vector<uint32_t> grp_q;
+    std::vector<int> grp_of_row(coo.size());
+    for (size_t z = 0; z < coo.size(); ++z) {
+      const CooRow& r = coo[z];
+      const int64_t key = ((int64_t)r.c * NQ + r.q2) * NQ + r.q3;
+      auto it = gid.find(key);
+      if (it == gid.end()) {
+        it = gid.emplace(key, (int)grp_c.size()).first;
+        grp_c.push_back(r.c);
+        grp_q.push_back((uint32_t)r.q2 | ((uint32_t)r.q3 << 16));
+      }
+      grp_of_row[z] = it->second;
+    }
+    for (size_t i = 0; i < order.size(); ++i) row_grp[i] = grp_of_row[order[i]];
+    h->rad_groups = (int)grp_c.size();
+    if (!upload(h, h->d_rad_grp_c, grp_c, s) || !upload(h, h->d_rad_grp_q, grp_q, s) ||
+        !upload(h, h->d_rad_q1ptr, q1ptr, s) || !upload(h, h->d_rad_row_grp, row_grp, s) ||
+        !upload(h, h->d_rad_row_g, eg, s))
+      return false;
+  }
   // ---- merged channels (l2 <= l3), in paper order (sorted by l1)
   std::vector<int> cidx((L + 1) * (L + 1) * (L + 1), -1);
   for (int c = 0; c < h->NT; ++c) {
@@ -399,8 +426,8 @@ static wefq_status new_core(int32_t model, double gamma_in, double b0, int32_t K
   }
   if (!(gamma >= 0.0 && gamma <= 2.0)) return fail(WEFQ_EINVAL, "gamma must lie in [0, 2]");
   unsigned prec = precisions ? precisions : (WEFQ_FP64 | WEFQ_FP32 | WEFQ_BF16X3);
-  if (prec & ~31u) return fail(WEFQ_EINVAL, "unknown precision bits");
-  if (prec & WEFQ_FP64_NAIVE) prec |= WEFQ_FP64;
+  if (prec & ~63u) return fail(WEFQ_EINVAL, "unknown precision bits");
+  if (prec & (WEFQ_FP64_NAIVE | WEFQ_PREP_RADIAL)) prec |= WEFQ_FP64;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(WEFQ_EHIP, "no HIP device available");
   if (device < 0 || device >= ndev) return fail(WEFQ_EINVAL, "device ordinal out of range");
@@ -469,6 +496,7 @@ wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info) {
   info->model = h->model;
   info->n_beta = (int64_t)h->beta.size();
   for (int j = 0; j < WEFQ_MAX_BETA; ++j) info->beta[j] = j < (int)h->beta.size() ? h->beta[j] : 0.0;
+  info->radial_groups = h->rad_groups;
   return WEFQ_OK;
 }
 
@@ -603,6 +631,37 @@ wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* 
     e = launch_apply_fp64(h, (const double*)f, (double*)Q, B, ld_f, ld_q, (hipStream_t)stream);
   else
     e = launch_apply_mfma(h, precision, f, Q, B, ld_f, ld_q, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return WEFQ_OK;
+}
+
+static const int64_t kRadialMaxChunk = 65536;
+
+wefq_status wefq_radial_workspace(wefq_handle h, int64_t chunk, int64_t* bytes) {
+  if (!h || !bytes) return fail(WEFQ_EINVAL, "null handle or output pointer");
+  if (!(h->precisions & WEFQ_PREP_RADIAL)) return fail(WEFQ_EINVAL, "the core was built without WEFQ_PREP_RADIAL");
+  if (chunk < 1) return fail(WEFQ_EINVAL, "chunk must be >= 1");
+  const int64_t c = std::min<int64_t>((chunk + 63) / 64 * 64, kRadialMaxChunk);
+  *bytes = c * radial_bytes_per_cell(h);
+  return WEFQ_OK;
+}
+
+wefq_status wefq_apply_Q_radial(wefq_handle h, const double* f, double* Q, int64_t B, int64_t ld_f, int64_t ld_q,
+                                void* work, int64_t work_bytes, void* stream) {
+  wefq_status st = check_batch(h, WEFQ_FP64, f, Q, B, ld_f, ld_q);
+  if (st != WEFQ_OK || B == 0) return st;
+  if (!(h->precisions & WEFQ_PREP_RADIAL)) return fail(WEFQ_EINVAL, "the core was built without WEFQ_PREP_RADIAL");
+  if (!Q) return fail(WEFQ_EINVAL, "null output pointer");
+  if (!work || ((uintptr_t)work & 255)) return fail(WEFQ_EINVAL, "workspace must be non-null and 256-byte aligned");
+  const int64_t per_cell = radial_bytes_per_cell(h);
+  const int64_t chunk = std::min<int64_t>(work_bytes / per_cell / 64 * 64, kRadialMaxChunk);
+  if (chunk < 64) return fail(WEFQ_EINVAL, "workspace smaller than one 64-cell chunk");
+  const char* fb = (const char*)f; const char* qb = (const char*)Q; const char* wb = (const char*)work;
+  const size_t fn = (size_t)B * ld_f * 8, qn = (size_t)B * ld_q * 8, wn = (size_t)chunk * per_cell;
+  if ((fb < qb + qn && qb < fb + fn) || (fb < wb + wn && wb < fb + fn) || (qb < wb + wn && wb < qb + qn))
+    return fail(WEFQ_EINVAL, "f, Q and the workspace must not overlap");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+  hipError_t e = launch_apply_radial(h, f, Q, B, ld_f, ld_q, work, chunk, (hipStream_t)stream);
   if (e != hipSuccess) return fail(WEFQ_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
   return WEFQ_OK;
 }

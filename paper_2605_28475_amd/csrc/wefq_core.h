@@ -25,6 +25,14 @@ struct wefq_core {
   std::vector<double> R64raw;          // before the invariant-row zeroing (bilinear tables, serialization)
 
   // FP64 plain path: COO rows grouped by q1 (CSR), paper channel ids
+  // radial-first ordering (reference path): distinct (channel, q2, q3) groups of the table
+  int rad_groups = 0;
+  int* d_rad_grp_c = nullptr;          // [rad_groups]
+  uint32_t* d_rad_grp_q = nullptr;     // [rad_groups] q2 | q3 << 16
+  int* d_rad_q1ptr = nullptr;          // [NQ + 1]
+  int* d_rad_row_grp = nullptr;        // [N_G], rows grouped by q1
+  double* d_rad_row_g = nullptr;       // [N_G]
+
   double* dR64 = nullptr;
   int* d_q1ptr = nullptr;              // NQ + 1
   int* d_ent_c = nullptr;              // N_G
@@ -154,5 +162,10 @@ hipError_t launch_apply_qfg(const wefq_core* h, int precision, const void* f, co
                             int64_t B, int64_t ldf, int64_t ldg, int64_t ldo, hipStream_t s);
 hipError_t launch_check(const wefq_core* h, int precision, const void* Q, int64_t B,
                         int64_t ldq, hipStream_t s);
+// Radial-first ordering, FP64 (radial.hip; needs the WEFQ_PREP_RADIAL tables).  work holds
+// chunk * radial_bytes_per_cell(h) bytes; chunk is a multiple of 64.
+int64_t radial_bytes_per_cell(const wefq_core* h);
+hipError_t launch_apply_radial(const wefq_core* h, const double* f, double* Q, int64_t B, int64_t ldf, int64_t ldq,
+                               void* work, int64_t chunk, hipStream_t s);
 
 }  // namespace wefq
