@@ -102,11 +102,13 @@ __host__ __device__ inline int tile_upper_row(int NK, int H, int TB) {
 }
 
 // Workgroups per cell tile for a launch of ntiles tiles: small batches split each tile's
-// work units over several workgroups, so that the launch still covers about two
-// workgroups per compute unit (latency mode); every workgroup keeps at least 4 units
-// for its 8 waves.
+// work units over several workgroups, so that the launch still covers about one
+// workgroup per compute unit (latency mode); every workgroup keeps at least 4 units
+// for its 8 waves.  (Measured at K = L = 8, 12 and 16: a second split workgroup per
+// compute unit costs more than it hides, since the tile fills the LDS at K >= 12 and
+// 8 waves keep the CU busy at K = 8.)
 inline int tile_splits(const wefq_core* h, int64_t ntiles) {
-  const int64_t target = 2 * (int64_t)h->cu_count;
+  const int64_t target = (int64_t)h->cu_count;
   if (ntiles <= 0 || ntiles >= target) return 1;
   const int64_t want = (target + ntiles - 1) / ntiles;
   const int64_t cap = h->nunits / 4 > 1 ? h->nunits / 4 : 1;

@@ -136,3 +136,25 @@ def test_angular_core_serialization(tmp_path):
     assert b.beta == BETA and b.gamma == a.gamma
     assert np.array_equal(a.download_R(), b.download_R())
     b.close()
+
+
+def test_maxwell_spectrum_at_largest_truncation():
+    """K = L = 16 (4,913 modes), where the two-input FP64 kernel does not fit LDS: the
+    linearized operator by polarization of the FP64 apply, L e_j = Q(e0 + e_j) - Q(e0) - Q(e_j),
+    against the Wang Chang-Uhlenbeck eigenvalues of the angular factor."""
+    K = L = 16
+    beta = EVEN
+    core = wefq.Core("mm", K, L, device=0, beta=beta, precisions=("fp64",))
+    N = core.N
+    e0 = torch.zeros((N, N), dtype=torch.float64, device=dev())
+    e0[:, 0] = 1.0
+    d = torch.eye(N, dtype=torch.float64, device=dev())
+    q = lambda x: core.apply_Q(x, precision="fp64")
+    Lm = (q(e0 + d) - q(e0) - q(d)).cpu().numpy().T
+    lam = np.array([_wcu_beta(k, l, beta) for l in range(L + 1) for m in range(-l, l + 1) for k in range(K + 1)])
+    scale = np.abs(lam).max()
+    err_diag = np.abs(np.diag(Lm) - lam).max() / scale
+    err_off = np.abs(Lm - np.diag(np.diag(Lm))).max() / scale
+    say(f"[wcu] K=L=16 beta={beta}: diag {err_diag:.2e} off {err_off:.2e}")
+    assert err_diag < 1e-11 and err_off < 1e-11
+    core.close()
