@@ -11,7 +11,7 @@ from oracle import apply as oapply
 from oracle_cache import coo, core_zeroed
 
 import paper_2605_28475_amd as wefq
-from paper_2605_28475_amd import synth
+from paper_2605_28475_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -158,3 +158,22 @@ def test_maxwell_spectrum_at_largest_truncation():
     say(f"[wcu] K=L=16 beta={beta}: diag {err_diag:.2e} off {err_off:.2e}")
     assert err_diag < 1e-11 and err_off < 1e-11
     core.close()
+
+
+def test_largest_angular_degree_and_zero_kernel():
+    """n_beta = WEFQ_MAX_BETA (degree 32) against the oracle; beta = 0 gives a zero operator."""
+    dev()
+    K, L = 2, 3
+    beta = tuple(1.0 / (1 + j) ** 2 for j in range(_lib.MAX_BETA))
+    core = wefq.Core("hs", K, L, device=0, beta=beta, precisions=("fp64",))
+    assert core.beta == beta
+    R = core.download_R()
+    ref = core_zeroed(K, L, 1.0, beta=beta).reshape(R.shape)
+    say(f"[core] degree 32: {rel_err(R, ref):.2e}")
+    assert rel_err(R, ref) < 1e-12
+    core.close()
+    zero = wefq.Core("vhs", 4, 4, gamma=0.5, device=0, beta=(0.0,), precisions=("fp64", "fp32"))
+    assert np.all(zero.download_R() == 0.0)
+    f = torch.tensor(synth.perturbed_maxwellian(4, 4, 3, seed=2), device=dev())
+    assert torch.all(zero.apply_Q(f, precision="fp64") == 0)
+    zero.close()

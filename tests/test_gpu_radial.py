@@ -90,3 +90,18 @@ def test_radial_first_errors():
     assert L_.wefq_apply_Q_radial(plain.handle, fp, qp, 4, N, N, wp, per64, s) == _lib.WEFQ_EINVAL
     plain.close()
     torch.cuda.synchronize()
+
+
+def test_radial_first_at_largest_truncation():
+    """K = L = 16: 430,529 groups, 58.5 MB of workspace per cell; 70 cells in two chunks,
+    against the FP64 angular-first kernel."""
+    K = L = 16
+    core = wefq.Core("hs", K, L, device=0, precisions=("fp64", "radial"))
+    assert core.info["radial_groups"] > 400000
+    f = torch.tensor(synth.perturbed_maxwellian(K, L, 70, seed=12), device=dev())
+    a = core.apply_Q(f, precision="fp64").cpu().numpy()
+    r = core.apply_Q_radial(f, chunk=64).cpu().numpy()
+    say(f"[radial vs angular] K=L=16: {rel_err(r, a):.2e}")
+    assert rel_err(r, a) < 1e-12
+    assert np.all(r[:, invariant_indices(K, L)] == 0.0)
+    core.close()
