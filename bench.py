@@ -229,12 +229,51 @@ def main():
                                 "normwise_fp32": float(np.linalg.norm(q32.cpu().numpy() - ref) / np.linalg.norm(ref)),
                                 "normwise_bf16x3": float(np.linalg.norm(q16.cpu().numpy() - ref) / np.linalg.norm(ref))}
         del q64
+        out["config1_latency"] = bench_single_cell(torch, wefq, synth, stream)
+        out["config2"] = bench_k8(torch, wefq, synth, stream)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(K, L, gamma, c, args.cpu_budget)
     out["host_cpu"] = {"cpu_count": os.cpu_count()}
     core.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_single_cell(torch, wefq, synth, stream):
+    """One hard-sphere cell at K = L = 3 in FP64: launch-to-completion latency of apply_Q
+    (HIP events around each call, 200 calls) and the conservation check."""
+    dev = torch.device("cuda:0")
+    core = wefq.Core("hs", 3, 3, device=0, precisions=("fp64",))
+    f = torch.tensor(synth.perturbed_maxwellian(3, 3, 1, seed=synth.BASE_SEED + 1), device=dev)
+    q = torch.empty_like(f)
+    core.apply_Q(f, out=q, precision="fp64")
+    ms, _ = time_steps(lambda: core.apply_Q(f, out=q, precision="fp64"), 200, stream, torch)
+    cons = core.check_conservation(q, precision="fp64")
+    core.close()
+    return {"workload": "hs_K3L3_B1_fp64", "p50_ms": float(np.percentile(ms, 50)),
+            "p99_ms": float(np.percentile(ms, 99)), "conservation_max_abs": cons}
+
+
+def bench_k8(torch, wefq, synth, stream):
+    """Maxwell molecules and hard spheres at K = L = 8, 4,096 cells: FP32 and FP64 (the same
+    tiled kernel) cells/s and the FP32 error against FP64."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, gamma in (("mm", 0.0), ("hs", 1.0)):
+        core = wefq.Core(name, 8, 8, device=0, precisions=("fp64", "fp32"))
+        f64 = torch.tensor(synth.perturbed_maxwellian(8, 8, 4096, seed=synth.BASE_SEED + 2), device=dev)
+        f32 = f64.float()
+        q64, q32 = torch.empty_like(f64), torch.empty_like(f32)
+        core.apply_Q(f64, out=q64, precision="fp64")
+        core.apply_Q(f32, out=q32, precision="fp32")
+        ms64, _ = time_steps(lambda: core.apply_Q(f64, out=q64, precision="fp64"), 50, stream, torch)
+        ms32, _ = time_steps(lambda: core.apply_Q(f32, out=q32, precision="fp32"), 50, stream, torch)
+        err = float((q32.double() - q64).abs().max().item() / q64.abs().max().item())
+        res[name] = {"fp32_cells_per_s": 4096 / (np.mean(ms32) * 1e-3), "fp64_cells_per_s": 4096 / (np.mean(ms64) * 1e-3),
+                     "fp32_p99_ms": float(np.percentile(ms32, 99)), "fp64_p99_ms": float(np.percentile(ms64, 99)),
+                     "fp32_max_rel_err_vs_fp64": err}
+        core.close()
+    return {"workload": "mm_and_hs_K8L8_B4096"} | res
 
 
 # angular factors of the build workload: Legendre coefficients of beta(cos chi)
