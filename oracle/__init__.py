@@ -15,5 +15,7 @@ basis      Laguerre x real-spherical-harmonic basis (Section 2.2).
 gaunt      Real Gaunt table, channel list, COO routing table (Section 4.1-4.2).
 weakform   Brute-force 8-D exact quadrature of the weak-form tensor (Section 2.3).
 core       Exact reduced radial core R and its invariant zeroing (Sections 3, 4.4).
-apply      The factorized discrete sum for Q, evaluated literally (Section 4.5).
+apply      The factorized discrete sum for Q, evaluated literally (Section 4.5); the
+           bilinear form Q(f, g) and the Jacobian-vector product.
+rk         Explicit Runge-Kutta integration of dc/dt = Q(c) (Section 5).
 """
