@@ -172,8 +172,9 @@ wefq_status wefq_apply_Q_radial(wefq_handle h, const double* f, double* Q, int64
  * WEFQ_FP64 and float for WEFQ_FP32 (the two precisions offered), aligned to the
  * element size; c and d may alias each other but not out.  out is overwritten, its
  * invariant rows are exactly 0.  Asynchronous on stream; allocates nothing.  Both
- * inputs are staged in LDS, so the cell tile is at most half that of wefq_apply_Q;
- * WEFQ_EUNSUPPORTED when two tiles of 4 cells do not fit (FP64 at Kmax = Lmax = 16). */
+ * inputs are staged in LDS, so the cell tile is at most half that of wefq_apply_Q: FP64
+ * at Kmax = Lmax >= 13 runs tiles of 2 cells with 8 output states per column group, which
+ * fit up to 16.  WEFQ_EUNSUPPORTED when even those do not fit LDS. */
 wefq_status wefq_apply_J(wefq_handle h, int32_t precision, const void* c, const void* d, void* out, int64_t B,
                          int64_t ld_c, int64_t ld_d, int64_t ld_out, void* stream);
 

@@ -684,7 +684,9 @@ static wefq_status check_two(wefq_handle h, int32_t precision, const void* c, co
     const size_t inn = (size_t)B * (in == c ? ld_c : ld_d) * es;
     if (ib < ob + on && ob < ib + inn) return fail(WEFQ_EINVAL, "the output must not overlap c or d");
   }
-  if (2 * tile_lds_bytes(h, 4, es) > (size_t)h->lds_limit)
+  // the smallest two-input tile: 2 cells x 8 output states (FP64, H >= 7), else 4 x 4
+  const int max_slots = (precision == WEFQ_FP64 && h->H >= 7) ? 8 : 4;
+  if (2 * tile_lds_bytes(h, max_slots, es) > (size_t)h->lds_limit)
     return fail(WEFQ_EUNSUPPORTED, "two coefficient tiles do not fit in LDS for this truncation");
   return WEFQ_OK;
 }

@@ -33,6 +33,10 @@ static hipError_t launch_jvp_t(const MfmaParams& p, bool anti, int64_t ntiles, s
   return hipGetLastError();
 }
 
+// Eight output states per column group (tiles of 2 cells) exist for FP64 at H >= 7 only:
+// there two FP64 tiles of 4 cells no longer fit LDS (K = L >= 13).  With H >= 8 a work unit
+// holds 4 output states, so half of the columns stay idle; the shape trades speed for
+// reaching the largest truncations.
 template <int H, int RT, int MODE>
 static hipError_t launch_jvp_s(const MfmaParams& p, bool anti, int slots, int64_t ntiles, size_t lds,
                                hipStream_t s) {
@@ -40,6 +44,9 @@ static hipError_t launch_jvp_s(const MfmaParams& p, bool anti, int slots, int64_
     case 1: return launch_jvp_t<H, 1, RT, MODE>(p, anti, ntiles, lds, s);
     case 2: return launch_jvp_t<H, 2, RT, MODE>(p, anti, ntiles, lds, s);
     case 4: return launch_jvp_t<H, 4, RT, MODE>(p, anti, ntiles, lds, s);
+    case 8:
+      if constexpr (MODE == 2 && H >= 7) return launch_jvp_t<H, 8, RT, MODE>(p, anti, ntiles, lds, s);
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
@@ -68,8 +75,10 @@ static hipError_t launch_two(const wefq_core* h, bool anti, int precision, const
   if (mode != 0 && mode != 2) return hipErrorInvalidValue;
   const size_t elem = mode == 2 ? 8 : 4;
   int slots = 0;
-  for (int sl : {1, 2, 4})
+  for (int sl : {1, 2, 4, 8}) {
+    if (sl == 8 && (mode != 2 || h->H < 7)) break;
     if (2 * tile_lds_bytes(h, sl, elem) <= (size_t)h->lds_limit) { slots = sl; break; }
+  }
   if (slots == 0) return hipErrorInvalidValue;
   MfmaParams p;
   p.f = f; p.g = g; p.Q = out; p.B = B; p.ldf = ldf; p.ldg = ldg; p.ldq = ldo;

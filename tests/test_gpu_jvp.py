@@ -51,7 +51,8 @@ def test_jvp_matches_oracle(K, L, model, gamma, B, prec):
     assert np.all(got[:, invariant_indices(K, L)] == 0.0)
 
 
-@pytest.mark.parametrize("K,L,model,gamma", [(12, 12, "vhs", 0.5), (16, 16, "hs", 1.0)])
+@pytest.mark.parametrize("K,L,model,gamma", [(12, 12, "vhs", 0.5), (13, 13, "mm", 0.0), (14, 14, "hs", 1.0),
+                                             (16, 16, "hs", 1.0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_jvp_polarization_large(K, L, model, gamma, prec):
     """At sizes the oracle does not reach in seconds: J(c) d = Q(c + d) - Q(c) - Q(d), with
@@ -59,12 +60,6 @@ def test_jvp_polarization_large(K, L, model, gamma, prec):
     core = gpu_core(model, K, L, gamma)
     c = synth.perturbed_maxwellian(K, L, 3, seed=synth.BASE_SEED + 71)
     d = 0.05 * np.random.default_rng(K).standard_normal(c.shape)
-    if prec == "fp64" and K == 16:
-        # two FP64 tiles of 4 cells need 314 KB of LDS: refused with a clear status
-        with pytest.raises(wefq.WefqError) as err:
-            jvp(core, c, d, prec)
-        assert err.value.status == _lib.WEFQ_EUNSUPPORTED
-        return
     c_in = tensor(c, prec).cpu().numpy().astype(np.float64)
     d_in = tensor(d, prec).cpu().numpy().astype(np.float64)
     q = lambda x: core.apply_Q(tensor(x, "fp64"), precision="fp64").cpu().numpy()
@@ -177,3 +172,17 @@ def test_bilinear_needs_prepared_tables():
         core.apply_Qfg(c, c, precision="fp64")
     assert err.value.status == _lib.WEFQ_EINVAL
     core.close()
+
+
+@pytest.mark.parametrize("K,L", [(13, 13), (16, 16)])
+def test_bilinear_large_fp64_against_fp32_and_identities(K, L):
+    """FP64 Q(f, g) where it runs on tiles of 2 cells: Q(f, f) = Q(f) (the FP64 apply),
+    Q(f, g) + Q(g, f) = J(f) g, and agreement with the FP32 bilinear form."""
+    core = gpu_core("hs", K, L, 1.0)
+    f = synth.perturbed_maxwellian(K, L, 5, seed=41)
+    g = synth.perturbed_maxwellian(K, L, 5, seed=42)
+    q = core.apply_Q(tensor(f, "fp64"), precision="fp64").cpu().numpy()
+    assert rel_err(qfg(core, f, f, "fp64"), q) < 1e-12
+    fg, gf = qfg(core, f, g, "fp64"), qfg(core, g, f, "fp64")
+    assert rel_err(fg + gf, jvp(core, f, g, "fp64")) < 1e-12
+    assert rel_err(qfg(core, f, g, "fp32"), fg) < 1e-5
