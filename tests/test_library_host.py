@@ -109,3 +109,24 @@ def test_core_load_rejects_bad_files_before_device_work(tmp_path):
     assert L_.wefq_core_load(str(empty).encode(), 0, 0, None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
     assert L_.wefq_core_save(None, missing) == _lib.WEFQ_EINVAL
     assert not h.value
+
+
+def test_header_compiles_as_plain_c(tmp_path):
+    """include/wefq.h is a C header: it compiles with a C99 compiler, pedantic, no C++."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "wefq.h"\n'
+                   "int main(void) {\n"
+                   "  wefq_core_desc d = {0};\n"
+                   "  wefq_core_info i;\n"
+                   "  (void)i;\n"
+                   "  return d.n_beta + WEFQ_MAX_BETA - 33;\n"
+                   "}\n")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    res = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc, "-c", str(src),
+                          "-o", str(tmp_path / "use.o")], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
