@@ -130,3 +130,13 @@ def test_header_compiles_as_plain_c(tmp_path):
     res = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc, "-c", str(src),
                           "-o", str(tmp_path / "use.o")], capture_output=True, text=True)
     assert res.returncode == 0, res.stderr
+
+
+def test_no_fallback_without_the_library(monkeypatch):
+    """Without libwefq.so every entry raises ImportError: there is no CPU path to fall back on."""
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libwefq.so")
+    with pytest.raises(ImportError):
+        wefq.Core("hs", 2, 2, device=0)
+    with pytest.raises(ImportError):
+        wefq.host_coo(2)
