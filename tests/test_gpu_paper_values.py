@@ -1,0 +1,64 @@
+"""The GPU path against numbers the paper prints, with no oracle in between: the Wang
+Chang-Uhlenbeck spectrum of Table 3 and the Chapman-Enskog viscosity factors of Table 4,
+both from the linearized operator J(e_000) formed by wefq_apply_J in FP64."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import dev, say, torch
+from oracle_cache import golden
+
+import paper_2605_28475_amd as wefq
+
+pytestmark = pytest.mark.gpu
+
+
+def linearized(core, cols=None):
+    """Columns J(e_000) e_j of the linearized operator (all j, or the given ones), FP64."""
+    N = core.N
+    cols = np.arange(N) if cols is None else np.asarray(cols)
+    c = torch.zeros((len(cols), N), dtype=torch.float64, device=dev())
+    c[:, 0] = 1.0
+    d = torch.zeros_like(c)
+    d[torch.arange(len(cols)), torch.as_tensor(cols, device=dev())] = 1.0
+    return core.apply_J(c, d, precision="fp64").cpu().numpy().T        # [N, len(cols)]
+
+
+def test_table3_wang_chang_uhlenbeck_spectrum():
+    """Maxwell molecules, K = 4, L = 6: eigenvalues over |lambda_6|, sorted, against Table 3
+    (within the printed difference bounds), and lambda_6 = -4 pi b0 / 3 at b0 = 1/(4 pi)."""
+    K, L = 4, 6
+    core = wefq.Core("mm", K, L, device=0, precisions=("fp64",))
+    Lm = linearized(core)
+    ev = np.linalg.eigvals(Lm)
+    assert np.abs(ev.imag).max() < 1e-13
+    ev = np.sort(ev.real)[::-1]
+    ratio = ev / abs(ev[5])
+    for first, last, r, bound in golden("table3_wcu.txt"):
+        seg = ratio[int(first) - 1:int(last)]
+        assert np.abs(seg - float(r)).max() <= max(float(bound), 1e-15) * 10
+    assert ratio.min() >= -3.0
+    assert abs(ev[5] - (-1.0 / 3.0)) < 1e-13
+    core.close()
+
+
+def test_table4_chapman_enskog_viscosity():
+    """Hard spheres, K_max = 8, L = 2: f_mu^(K) = L_00 [(L_{kk'})_{k,k' <= K}^{-1}]_00 on the l = 2
+    block of the GPU's linearized operator, against Table 4 (6 printed digits) and the exact
+    K = 1 value 205/202."""
+    Kmax, L = 8, 2
+    core = wefq.Core("hs", Kmax, L, device=0, precisions=("fp64",))
+    NK = Kmax + 1
+    q = 2 * 2 + 2 + 0                                          # (l, m) = (2, 0)
+    cols = q * NK + np.arange(NK)
+    L2 = linearized(core, cols)[q * NK:(q + 1) * NK, :]        # rows (k1, 2, 0), columns (k, 2, 0)
+    fmu = [L2[0, 0] * np.linalg.inv(L2[:K + 1, :K + 1])[0, 0] for K in range(Kmax + 1)]
+    say("[table4] " + " ".join(f"{x:.7f}" for x in fmu))
+    table = golden("table4_viscosity.txt")
+    for K, val in table[:-1]:
+        assert abs(fmu[int(K)] - float(val)) <= 5e-7
+    assert abs(fmu[1] - 205 / 202) < 1e-12
+    assert all(b > a for a, b in zip(fmu, fmu[1:]))
+    assert 1.016028 < fmu[8] <= float(table[-1][1]) + 5e-7
+    core.close()
