@@ -62,3 +62,34 @@ def test_table4_chapman_enskog_viscosity():
     assert all(b > a for a, b in zip(fmu, fmu[1:]))
     assert 1.016028 < fmu[8] <= float(table[-1][1]) + 5e-7
     core.close()
+
+
+def test_stress_relaxation_follows_linear_theory():
+    """Section 5's transient stress relaxation, hard spheres, K = L = 8: a Maxwellian with a
+    small (k, l, m) = (0, 2, 0) shear perturbation, RK4 in FP64 on the GPU.  The shear mode
+    follows the linear prediction [exp(L_2 t)]_{00} from the GPU's own linearized operator to
+    O(eps); energy cascades into the k > 0 modes of l = 2; the invariants stay exactly put."""
+    from scipy.linalg import expm
+    K = L = 8
+    NK = K + 1
+    core = wefq.Core("hs", K, L, device=0, precisions=("fp64",))
+    q = 6                                                      # (l, m) = (2, 0)
+    cols = q * NK + np.arange(NK)
+    L2 = linearized(core, cols)[q * NK:(q + 1) * NK, :]
+    eps, dt, n = 1e-4, 0.05, 60
+    c0 = np.zeros((1, core.N))
+    c0[0, 0] = 1.0
+    c0[0, q * NK] = eps
+    c = torch.tensor(c0, device=dev())
+    inv = core.rk_integrate(c, dt, n, scheme="rk4", precision="fp64")
+    got = c.cpu().numpy()[0]
+    lin = eps * expm(L2 * (dt * n))[:, 0]                      # the whole l = 2, m = 0 block
+    say(f"[stress] t={dt * n}: shear {got[q * NK] / eps:.6f} linear {lin[0] / eps:.6f}")
+    assert inv == 0.0
+    assert abs(got[q * NK] - lin[0]) < 1e-3 * eps              # nonlinear terms are O(eps^2)
+    assert np.abs(got[q * NK:(q + 1) * NK] - lin).max() < 1e-3 * eps
+    assert got[q * NK] < 0.9 * eps                             # it has decayed
+    assert np.abs(got[q * NK + 1:(q + 1) * NK]).max() > 1e-3 * eps   # cascade into k > 0
+    inv_idx = [0, 1, NK, 2 * NK, 3 * NK]
+    assert np.array_equal(got[inv_idx], c0[0, inv_idx])
+    core.close()
