@@ -118,6 +118,11 @@ wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handl
 
 wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info);
 
+/* Flat index of the basis function phi_klm (Section 2.2) in a core's coefficient vectors:
+ * *n = (l*l + l + m) * NK + k.  EINVAL unless 0 <= k <= Kmax, 0 <= l <= Lmax, |m| <= l.
+ * Host only. */
+wefq_status wefq_mode_index(wefq_handle h, int32_t k, int32_t l, int32_t m, int64_t* n);
+
 /* Copy the zeroed FP64 core to host memory: R[c][k1][k2][k3], c in the paper's
  * channel order (l1 outer, l2, l3 inner), count = N_T * NK^3 doubles. */
 wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count);

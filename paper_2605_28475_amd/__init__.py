@@ -117,6 +117,12 @@ class Core:
                                            _stream_ptr(stream, f2.device)))
         return out[0] if squeeze else out
 
+    def mode_index(self, k, l, m):
+        """Flat index n = (l^2 + l + m) NK + k of phi_klm in a coefficient vector (wefq_mode_index)."""
+        n = ctypes.c_int64()
+        _lib.check(_lib.lib().wefq_mode_index(self._h, int(k), int(l), int(m), ctypes.byref(n)))
+        return n.value
+
     def radial_workspace_bytes(self, chunk):
         """Workspace bytes of apply_Q_radial for chunks of `chunk` cells (wefq_radial_workspace)."""
         n = ctypes.c_int64()

@@ -55,6 +55,8 @@ _SIGNATURES = [
     ("wefq_core_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     ("wefq_core_load", ctypes.c_int, [ctypes.c_char_p, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_void_p)]),
+    ("wefq_mode_index", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int64)]),
     ("wefq_apply_Q", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p]),
     ("wefq_radial_workspace", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),

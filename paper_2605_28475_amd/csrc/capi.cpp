@@ -500,6 +500,14 @@ wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info) {
   return WEFQ_OK;
 }
 
+wefq_status wefq_mode_index(wefq_handle h, int32_t k, int32_t l, int32_t m, int64_t* n) {
+  if (!h || !n) return fail(WEFQ_EINVAL, "null handle or output pointer");
+  if (k < 0 || k > h->K || l < 0 || l > h->L || m < -l || m > l)
+    return fail(WEFQ_EINVAL, "mode (k, l, m) outside the truncation");
+  *n = (int64_t)(l * l + l + m) * h->NK + k;
+  return WEFQ_OK;
+}
+
 wefq_status wefq_core_download_R(wefq_handle h, double* host_R, int64_t count) {
   if (!h || !host_R) return fail(WEFQ_EINVAL, "null handle or output pointer");
   if (count != (int64_t)h->R64.size()) return fail(WEFQ_EINVAL, "count must equal N_T * NK^3");

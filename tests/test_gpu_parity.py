@@ -10,7 +10,7 @@ from oracle import core as ocore
 from oracle_cache import coo, core_zeroed
 
 import paper_2605_28475_amd as wefq
-from paper_2605_28475_amd import synth
+from paper_2605_28475_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -256,3 +256,18 @@ def test_rotation_equivariance_on_gpu(K, L, model, gamma):
         q = run(core, c, prec)
         qr = run(core, cr, prec)
         assert rel_err(qr, rotate(q, K, L, blocks)) < tol, prec
+
+
+def test_mode_index_matches_the_layout():
+    """wefq_mode_index gives n = (l^2 + l + m) NK + k, the oracle basis order, and refuses modes
+    outside the truncation."""
+    from oracle import basis
+    K, L = 5, 3
+    core = wefq.Core("hs", K, L, device=0, precisions=("fp64",))
+    for n, (k, l, m) in enumerate(basis.mode_table(K, L)):
+        assert core.mode_index(int(k), int(l), int(m)) == n
+    for bad in ((K + 1, 0, 0), (0, L + 1, 0), (0, 2, 3), (-1, 0, 0), (0, 1, -2)):
+        with pytest.raises(wefq.WefqError) as err:
+            core.mode_index(*bad)
+        assert err.value.status == _lib.WEFQ_EINVAL
+    core.close()

@@ -84,6 +84,8 @@ def test_error_paths_without_device():
     assert lib.wefq_build_core(ctypes.byref(desc), None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
     assert b"non-finite" in lib.wefq_last_error()
     assert lib.wefq_apply_Q(None, 1, None, None, 1, 1, 1, None) == _lib.WEFQ_EINVAL
+    n = ctypes.c_int64()
+    assert lib.wefq_mode_index(None, 0, 0, 0, ctypes.byref(n)) == _lib.WEFQ_EINVAL
     assert lib.wefq_destroy(None) == _lib.WEFQ_EINVAL
     n = ctypes.c_int64()
     assert lib.wefq_host_coo(17, ctypes.byref(n), None, None, None, None, None) == _lib.WEFQ_EUNSUPPORTED
