@@ -334,7 +334,7 @@ def bench_orderings(args, torch, wefq, synth):
         core.apply_Q(f, out=q, precision="fp64")
         ms_a, _ = time_steps(lambda: core.apply_Q(f, out=q, precision="fp64"), 10, stream, torch)
         per64 = core.radial_workspace_bytes(64)
-        chunk = max(64, min(B, (1 << 30) // per64 * 64))
+        chunk = max(64, min(B, (4 << 30) // per64 * 64))
         work = torch.empty(core.radial_workspace_bytes(chunk), dtype=torch.uint8, device=dev)
         qr = torch.empty_like(f)
         core.apply_Q_radial(f, out=qr, work=work)

@@ -101,10 +101,20 @@ __global__ __launch_bounds__(256) void radial_gather_kernel(RadialParams p) {
   if (n >= p.N) return;
   const int cell = (int)((wave % wpg) * 64 + (tid & 63));
   const int q1 = n / p.NK, k1 = n % p.NK;
-  double acc = 0.0;
+  // four independent partial sums keep four Psi loads in flight per lane
+  const double* col = p.psi + (int64_t)k1 * p.Bp + cell;
+  const int64_t gstride = (int64_t)p.NK * p.Bp;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   const int z1 = ((cint*)p.q1ptr)[q1 + 1];
-  for (int z = ((cint*)p.q1ptr)[q1]; z < z1; ++z)
-    acc += ((cdbl*)p.row_g)[z] * p.psi[((int64_t)((cint*)p.row_grp)[z] * p.NK + k1) * p.Bp + cell];
+  int z = ((cint*)p.q1ptr)[q1];
+  for (; z + 3 < z1; z += 4) {
+    a0 += ((cdbl*)p.row_g)[z] * col[((cint*)p.row_grp)[z] * gstride];
+    a1 += ((cdbl*)p.row_g)[z + 1] * col[((cint*)p.row_grp)[z + 1] * gstride];
+    a2 += ((cdbl*)p.row_g)[z + 2] * col[((cint*)p.row_grp)[z + 2] * gstride];
+    a3 += ((cdbl*)p.row_g)[z + 3] * col[((cint*)p.row_grp)[z + 3] * gstride];
+  }
+  for (; z < z1; ++z) a0 += ((cdbl*)p.row_g)[z] * col[((cint*)p.row_grp)[z] * gstride];
+  double acc = (a0 + a1) + (a2 + a3);
   if (invariant_row(q1, k1)) acc = 0.0;
   if (cell < p.nc) p.Q[(p.c0 + cell) * p.ldq + n] = acc;
 }
