@@ -89,3 +89,26 @@ def test_plan_rejects_bad_segments():
         wefq.Plan([(c, f, torch.empty_like(f))], precision="fp32", block=300)
     with pytest.raises(wefq.WefqError):
         wefq.Plan([(c, f, torch.empty_like(f), 3)], precision="fp32")
+
+
+def test_plan_with_anisotropic_cores():
+    """Segments whose cores carry an angular factor run in the same persistent launch and
+    give bitwise the standalone results."""
+    d = dev()
+    aniso = wefq.Core("hs", 8, 8, device=0, beta=(1.0, 0.5, 0.3, 0.1))
+    iso = core("vhs", 12, 0.5)
+    segs = []
+    for i, (c, K, B) in enumerate(((aniso, 8, 70), (iso, 12, 40), (aniso, 8, 3))):
+        f = torch.tensor(synth.perturbed_maxwellian(K, K, B, seed=2000 + i), dtype=torch.float32, device=d)
+        segs.append((c, f, torch.empty_like(f)))
+    refs = [c.apply_Q(f).clone() for c, f, _ in segs]
+    plan = wefq.Plan(segs, precision="fp32")
+    for replay in range(2):
+        for _, _, q in segs:
+            q.fill_(float("nan"))
+        plan.launch()
+        torch.cuda.synchronize()
+        for (c, f, q), r in zip(segs, refs):
+            assert torch.equal(q, r), f"replay {replay}"
+    plan.close()
+    aniso.close()
