@@ -271,3 +271,37 @@ def test_mode_index_matches_the_layout():
             core.mode_index(*bad)
         assert err.value.status == _lib.WEFQ_EINVAL
     core.close()
+
+
+def test_apply_q_argument_errors():
+    """Every refusal of wefq_apply_Q through the C-ABI, each checked before any launch (the
+    output stays untouched): null handle, unknown or unprepared precision, negative batch,
+    null pointers, leading dimensions below N, overlapping input and output."""
+    import ctypes
+    K = L = 3
+    core = wefq.Core("hs", K, L, device=0, precisions=("fp64",))
+    N = core.N
+    f = torch.tensor(synth.perturbed_maxwellian(K, L, 4, seed=6), device=dev())
+    q = torch.full_like(f, 3.0)
+    L_ = _lib.lib()
+    fp, qp = ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(q.data_ptr())
+    h = core.handle
+    cases = [
+        (None, _lib.FP64, fp, qp, 4, N, N),          # null handle
+        (h, 3, fp, qp, 4, N, N),                     # not a precision
+        (h, _lib.FP32, fp, qp, 4, N, N),             # precision not prepared
+        (h, _lib.FP64, fp, qp, -1, N, N),            # negative batch
+        (h, _lib.FP64, None, qp, 4, N, N),           # null input
+        (h, _lib.FP64, fp, None, 4, N, N),           # null output
+        (h, _lib.FP64, fp, qp, 4, N - 1, N),         # ld_f < N
+        (h, _lib.FP64, fp, qp, 4, N, N - 1),         # ld_q < N
+        (h, _lib.FP64, fp, fp, 4, N, N),             # Q aliases f
+        (h, _lib.FP64, fp, ctypes.c_void_p(f.data_ptr() + 8 * N), 4, N, N),   # overlap
+    ]
+    for args in cases:
+        assert L_.wefq_apply_Q(*args, None) == _lib.WEFQ_EINVAL, args
+        assert L_.wefq_last_error()
+    torch.cuda.synchronize()
+    assert torch.all(q == 3.0)
+    assert L_.wefq_apply_Q(h, _lib.FP64, fp, qp, 0, N, N, None) == _lib.WEFQ_OK      # empty batch
+    core.close()
