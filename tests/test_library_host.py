@@ -142,3 +142,47 @@ def test_no_fallback_without_the_library(monkeypatch):
         wefq.Core("hs", 2, 2, device=0)
     with pytest.raises(ImportError):
         wefq.host_coo(2)
+
+
+def _fnv1a(data):
+    h = 1469598103934665603
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _core_file(version, n_beta, beta0=1.0):
+    """A core file for K = 1, L = 0 (one channel, NK = 2): header, angular record for
+    version 2, then a zero payload with its FNV-1a checksum."""
+    import struct
+    payload = bytes(8 * 8)
+    angular = struct.pack("<ii33d", n_beta, 0, *([beta0] + [0.0] * 32)) if version == 2 else b""
+    header = struct.pack("<8sIIiiiiiiddqQQ", b"WEFQCORE", version, 80 + len(angular), 1, 1, 0, 1, 2, 0,
+                         1.0, 0.0, 10, 8, _fnv1a(payload))
+    return header + angular + payload
+
+
+def test_core_load_checks_the_angular_record(tmp_path):
+    """A version-2 (angular factor) file with n_beta outside [1, WEFQ_MAX_BETA] or a
+    non-finite coefficient is refused; a well-formed one passes every file check (and then
+    needs a device)."""
+    L_ = _lib.lib()
+    h = ctypes.c_void_p()
+    for n_beta in (0, _lib.MAX_BETA + 1, -3):
+        p = tmp_path / f"bad{n_beta}.wefq"
+        p.write_bytes(_core_file(2, n_beta))
+        assert L_.wefq_core_load(str(p).encode(), 0, 0, None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    p = tmp_path / "nan.wefq"
+    p.write_bytes(_core_file(2, 1, float("nan")))
+    assert L_.wefq_core_load(str(p).encode(), 0, 0, None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    assert b"non-finite" in L_.wefq_last_error()
+    p = tmp_path / "wrongsize.wefq"
+    p.write_bytes(_core_file(1, 0)[:80] + _core_file(2, 1)[80:])       # version 1 header, v2 body
+    assert L_.wefq_core_load(str(p).encode(), 0, 0, None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    for version in (1, 2):
+        p = tmp_path / f"good{version}.wefq"
+        p.write_bytes(_core_file(version, 1))
+        st = L_.wefq_core_load(str(p).encode(), 0, 0, None, ctypes.byref(h))
+        assert st in (_lib.WEFQ_OK, _lib.WEFQ_EHIP), L_.wefq_last_error()
+        if st == _lib.WEFQ_OK:
+            L_.wefq_destroy(h)
