@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void radial_psi_kernel(RadialParams p) {
       for (int k3 = 0; k3 < NK; ++k3) t += R[(k1 * NK + k2) * NK + k3] * f3[k3];
       acc += t * f2[k2];
     }
-    out[(int64_t)k1 * p.Bp] = acc;
+    __builtin_nontemporal_store(acc, out + (int64_t)k1 * p.Bp);   // streamed: read once, by pass 2
   }
 }
 
