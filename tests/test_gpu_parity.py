@@ -55,7 +55,9 @@ def test_core_k12_vhs_sampled_channels():
 
 @pytest.mark.parametrize("K,L,model,gamma,B", [(3, 3, "hs", 1.0, 1), (3, 3, "hs", 1.0, 37),
                                                (4, 4, "vhs", 0.5, 21), (8, 8, "hs", 1.0, 19),
-                                               (5, 3, "mm", 0.0, 17), (2, 7, "hs", 1.0, 5)])
+                                               (5, 3, "mm", 0.0, 17), (2, 7, "hs", 1.0, 5),
+                                               (0, 4, "hs", 1.0, 7), (6, 0, "vhs", 0.5, 9),
+                                               (0, 0, "mm", 0.0, 3), (1, 1, "hs", 1.0, 5)])
 @pytest.mark.parametrize("prec", ["fp64", "fp64_naive", "fp32", "bf16x3"])
 def test_apply_matches_oracle(K, L, model, gamma, B, prec):
     say(f"[apply] K={K} L={L} {model} B={B} {prec}")
