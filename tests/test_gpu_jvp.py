@@ -35,7 +35,8 @@ def jvp(core, c, d, prec):
 
 
 @pytest.mark.parametrize("K,L,model,gamma,B", [(3, 3, "hs", 1.0, 7), (4, 4, "vhs", 0.5, 19), (8, 8, "mm", 0.0, 5),
-                                               (5, 2, "hs", 1.0, 3), (2, 6, "vhs", 0.5, 4)])
+                                               (5, 2, "hs", 1.0, 3), (2, 6, "vhs", 0.5, 4), (0, 3, "hs", 1.0, 6),
+                                               (4, 0, "vhs", 0.5, 5)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_jvp_matches_oracle(K, L, model, gamma, B, prec):
     core = gpu_core(model, K, L, gamma)
@@ -124,7 +125,8 @@ def qfg(core, f, g, prec):
 
 
 @pytest.mark.parametrize("K,L,model,gamma,B", [(3, 3, "hs", 1.0, 6), (4, 4, "vhs", 0.5, 9), (8, 8, "mm", 0.0, 3),
-                                               (2, 6, "vhs", 0.5, 4), (5, 2, "hs", 1.0, 3)])
+                                               (2, 6, "vhs", 0.5, 4), (5, 2, "hs", 1.0, 3), (0, 3, "hs", 1.0, 4),
+                                               (4, 0, "mm", 0.0, 3)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_bilinear_matches_oracle(K, L, model, gamma, B, prec):
     """Q(f, g) against the oracle's literal bilinear sum with the core before the zeroing
