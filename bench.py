@@ -318,7 +318,8 @@ def bench_orderings(args, torch, wefq, synth):
     K = 4 and L = 2..13, 16,384 cells: naive (every table row contracts its NK^3 block; on
     2,048 cells), radial-first (the dense intermediate Psi through HBM, then one pass over the
     table) and angular-first (the tiled MFMA kernel).  The dense Cartesian contraction is not
-    run; its count, 2 N^3 FLOPs per cell, is given for reference."""
+    run; its count, 2 N^3 FLOPs per cell, is given for reference.  One more point compares
+    radial-first with angular-first at K = L = 12 (VHS 0.5, 1,024 cells)."""
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -360,11 +361,28 @@ def bench_orderings(args, torch, wefq, synth):
                      "rel_err_vs_angular": {"radial_first": err_r, "naive": err_n}})
         del f, q, qr, work, fn, qn
         core.close()
+    # the headline truncation: which ordering an apply should use at K = L = 12
+    log("[orderings] K=L=12 (1,024 cells)")
+    core = wefq.Core("vhs", 12, 12, gamma=0.5, device=0, precisions=("fp64", "radial"))
+    f = torch.tensor(synth.perturbed_maxwellian(12, 12, 1024, seed=synth.BASE_SEED + 18), device=dev)
+    q, qr = torch.empty_like(f), torch.empty_like(f)
+    core.apply_Q(f, out=q, precision="fp64")
+    ms_a, _ = time_steps(lambda: core.apply_Q(f, out=q, precision="fp64"), 5, stream, torch)
+    work = torch.empty(core.radial_workspace_bytes(256), dtype=torch.uint8, device=dev)
+    core.apply_Q_radial(f, out=qr, work=work)
+    ms_r, _ = time_steps(lambda: core.apply_Q_radial(f, out=qr, work=work), 2, stream, torch)
+    k12 = {"K": 12, "L": 12, "cells": 1024, "model": "vhs0.5",
+           "angular_first_cells_per_s": 1024 / (np.mean(ms_a) * 1e-3),
+           "radial_first_cells_per_s": 1024 / (np.mean(ms_r) * 1e-3),
+           "angular_vs_radial": float(np.mean(ms_r) / np.mean(ms_a)),
+           "rel_err_radial_vs_angular": (qr - q).abs().max().item() / q.abs().max().item()}
+    del f, q, qr, work
+    core.close()
     last = rows[-1]
     out = {"metric": "FP64 Q(f,f) cell-evals/sec by ordering, hard spheres, K = 4, L = 13",
            "value": last["angular_first_cells_per_s"], "unit": "cells/s", "n_gpus": 1, "higher_is_better": True,
            "dtype": "f64", "data": "synthetic", "config": {"workload": f"orderings_hs_K{K}_L2-13_B{B}", "cells": B},
-           "orderings": rows}
+           "orderings": rows, "headline_truncation": k12}
     print(json.dumps(out), flush=True)
 
 
