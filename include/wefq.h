@@ -116,6 +116,9 @@ typedef struct {
  * [0, WEFQ_MAX_BETA], a NULL beta with n_beta > 0 or a non-finite coefficient. */
 wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handle* out);
 
+/* Sizes and parameters of a built core (the counts of Sections 4.6-4.7 and Table 6, the
+ * merged counts of this implementation, device memory held, the angular factor).  Host
+ * only; info is caller-owned.  EINVAL for a null argument. */
 wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info);
 
 /* Flat index of the basis function phi_klm (Section 2.2) in a core's coefficient vectors:
@@ -202,8 +205,12 @@ wefq_status wefq_apply_Qfg(wefq_handle h, int32_t precision, const void* f, cons
 wefq_status wefq_check_conservation(wefq_handle h, int32_t precision, const void* Q,
                                     int64_t B, int64_t ld_q, double* max_abs, void* stream);
 
+/* Release every device and host resource of a core.  The caller must have synchronized
+ * the streams that used it (plans built on it must be destroyed first).  EINVAL for NULL. */
 wefq_status wefq_destroy(wefq_handle h);
 
+/* Message of the last non-OK status returned on the calling thread (thread-local; valid
+ * until the thread's next failing call).  Never NULL. */
 const char* wefq_last_error(void);
 
 /* Tile shape used by wefq_apply_Q for one precision of a core: slots = output
@@ -214,6 +221,8 @@ const char* wefq_last_error(void);
  * registers per lane, at 512 threads; the autotuner may replace it.  Each precision keeps its own shape.
  * Not thread-safe with concurrent applies of the same core. */
 wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32_t block);
+/* The shape wefq_apply_Q currently uses for a precision.  EINVAL for a null argument or a
+ * precision without tiles. */
 wefq_status wefq_tune_get(wefq_handle h, int32_t precision, int32_t* slots, int32_t* block);
 
 /* ---- uneven batches in one persistent launch (captured in a HIP graph) ---- */
@@ -244,7 +253,10 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
 wefq_status wefq_plan_launch(wefq_plan p, void* stream);
 /* The same two kernels launched directly, without the graph. */
 wefq_status wefq_plan_launch_direct(wefq_plan p, void* stream);
+/* The plan's work list length, dynamic LDS per workgroup and persistent grid size; any output
+ * pointer may be NULL.  EINVAL for a null plan. */
 wefq_status wefq_plan_info(wefq_plan p, int64_t* work_items, int64_t* lds_bytes, int64_t* grid);
+/* Release the plan (its graph and device work list); the caller synchronizes first. */
 wefq_status wefq_plan_destroy(wefq_plan p);
 
 /* ---- time integration: batched explicit Runge-Kutta stepping of dc/dt = Q(c) ---- */
