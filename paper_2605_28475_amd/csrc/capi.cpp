@@ -346,36 +346,47 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   // work units: (l1, up to GQ output states q1), largest estimated cost first.  Within
   // l1 the states are listed as m1, -m1 for m1 = 1..l1, then m1 = 0, so that a group
   // of output states sharing the MFMA columns holds slices of similar length.
-  h->GQ = H >= 8 ? 4 : 8;     // must match the kernel's units (gq_for)
   struct Unit { int l1, nq; int q[UNIT_STRIDE - 2]; double cost; };
-  std::vector<Unit> units;
-  for (int l1 = 0; l1 <= L; ++l1) {
-    std::vector<int> order;
-    for (int m = 1; m <= l1; ++m) { order.push_back(l1 * l1 + l1 + m); order.push_back(l1 * l1 + l1 - m); }
-    order.push_back(l1 * l1 + l1);
-    for (size_t i0 = 0; i0 < order.size(); i0 += h->GQ) {
-      Unit un{l1, 0, {}, 0.0};
-      un.nq = (int)std::min<size_t>(h->GQ, order.size() - i0);
-      for (int i = 0; i < un.nq; ++i) un.q[i] = order[i0 + i];
-      for (int m = chan_begin[l1]; m < chan_begin[l1 + 1]; ++m)
-        for (int i = 0; i < un.nq; ++i) {
-          const int si = slice_off[m] + un.q[i] - l1 * l1;
-          const int npair = (spair[si] - sptr[si]) / 2, nsingle = sptr[si + 1] - spair[si];
-          un.cost += (double)npair * (HH + 5 * H) + (double)nsingle * (HH + 3 * H) + HH * RT * 8.0;
-        }
-      units.push_back(un);
+  auto build_units = [&](int GQ, std::vector<int>& uarr, double& total_cost) -> int {
+    std::vector<Unit> units;
+    for (int l1 = 0; l1 <= L; ++l1) {
+      std::vector<int> order;
+      for (int m = 1; m <= l1; ++m) { order.push_back(l1 * l1 + l1 + m); order.push_back(l1 * l1 + l1 - m); }
+      order.push_back(l1 * l1 + l1);
+      for (size_t i0 = 0; i0 < order.size(); i0 += GQ) {
+        Unit un{l1, 0, {}, 0.0};
+        un.nq = (int)std::min<size_t>(GQ, order.size() - i0);
+        for (int i = 0; i < un.nq; ++i) un.q[i] = order[i0 + i];
+        for (int m = chan_begin[l1]; m < chan_begin[l1 + 1]; ++m)
+          for (int i = 0; i < un.nq; ++i) {
+            const int si = slice_off[m] + un.q[i] - l1 * l1;
+            const int npair = (spair[si] - sptr[si]) / 2, nsingle = sptr[si + 1] - spair[si];
+            un.cost += (double)npair * (HH + 5 * H) + (double)nsingle * (HH + 3 * H) + HH * RT * 8.0;
+          }
+        units.push_back(un);
+      }
     }
-  }
-  std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+    std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+    total_cost = 0.0;
+    for (auto& u : units) {
+      uarr.push_back(u.l1);
+      uarr.push_back(u.nq);
+      for (int i = 0; i < UNIT_STRIDE - 2; ++i) uarr.push_back(u.q[i]);
+      total_cost += u.cost;
+    }
+    return (int)units.size();
+  };
+  h->GQ = H >= 8 ? 4 : 8;     // must match the kernel's units (gq_for)
   std::vector<int> uarr;
-  h->tile_cost = 0.0;
-  for (auto& u : units) {
-    uarr.push_back(u.l1);
-    uarr.push_back(u.nq);
-    for (int i = 0; i < UNIT_STRIDE - 2; ++i) uarr.push_back(u.q[i]);
-    h->tile_cost += u.cost;
+  h->nunits = build_units(h->GQ, uarr, h->tile_cost);
+  // the FP64 two-input tiles of 2 cells carry 8 output states per column group: at H >= 8,
+  // where the units above hold 4, they get units of 8
+  if (H >= 8 && want64) {
+    std::vector<int> u8;
+    double c8 = 0.0;
+    h->nunits8 = build_units(8, u8, c8);
+    if (!upload(h, h->d_units8, u8, s)) return false;
   }
-  h->nunits = (int)units.size();
   if (!upload(h, h->d_units, uarr, s) || !upload(h, h->d_chan_begin, chan_begin, s) ||
       !upload(h, h->d_slice_off, slice_off, s) || !upload(h, h->d_sptr, sptr, s) ||
       !upload(h, h->d_spair, spair, s) ||

@@ -34,9 +34,8 @@ static hipError_t launch_jvp_t(const MfmaParams& p, bool anti, int64_t ntiles, s
 }
 
 // Eight output states per column group (tiles of 2 cells) exist for FP64 at H >= 7 only:
-// there two FP64 tiles of 4 cells no longer fit LDS (K = L >= 13).  With H >= 8 a work unit
-// holds 4 output states, so half of the columns stay idle; the shape trades speed for
-// reaching the largest truncations.
+// there two FP64 tiles of 4 cells no longer fit LDS (K = L >= 13).  At H >= 8, where the
+// apply's work units hold 4 output states, these launches take a second unit list with 8.
 template <int H, int RT, int MODE>
 static hipError_t launch_jvp_s(const MfmaParams& p, bool anti, int slots, int64_t ntiles, size_t lds,
                                hipStream_t s) {
@@ -89,9 +88,11 @@ static hipError_t launch_two(const wefq_core* h, bool anti, int precision, const
   p.Rt32 = anti ? h->d_Dt32 : h->d_Rt32; p.Rt64 = anti ? h->d_Dt64 : h->d_Rt64;
   p.R16_32 = anti ? h->d_D16_32 : h->d_R16_32; p.R16_64 = anti ? h->d_D16_64 : h->d_R16_64;
   p.Rhi = nullptr; p.Rlo = nullptr;
+  if (slots == 8 && h->d_units8) { p.units = h->d_units8; p.nunits = h->nunits8; }
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
   p.nsplit = tile_splits(h, ntiles);
+  if (p.nsplit > 1 && p.nsplit > p.nunits / 4) p.nsplit = p.nunits / 4 > 1 ? p.nunits / 4 : 1;
   const size_t lds = 2 * tile_lds_bytes(h, slots, elem);
   switch (h->H) {
     case 1: return launch_jvp_h<1>(p, anti, mode, slots, h->RT, ntiles, lds, s);

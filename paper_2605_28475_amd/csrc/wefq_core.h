@@ -63,6 +63,8 @@ struct wefq_core {
   uint16_t* d_Rlo = nullptr;
   int* d_units = nullptr;              // [nunits][UNIT_STRIDE]: l1, count, q1 values
   int nunits = 0;
+  int* d_units8 = nullptr;             // units of 8 output states (FP64 two-input tiles, H >= 8)
+  int nunits8 = 0;
   int GQ = 0;                          // q1 per unit
   double tile_cost = 0.0;              // estimated cost of one full 16-cell tile (scheduling only)
   int lds_limit = 0;                   // usable LDS bytes per workgroup

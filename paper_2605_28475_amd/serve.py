@@ -114,6 +114,10 @@ class Server:
                         done_ev[r] = ev
                         if keep_outputs:
                             outputs[r] = q.clone()
+                    if keep_outputs:
+                        # the clones run on this stream; the block may be reused by a launch
+                        # on another stream as soon as it is released, so they finish first
+                        torch.cuda.current_stream(self.dev).synchronize()
                     self.arena.release(*blk)
                 else:
                     still.append((ev, qs, blk))
