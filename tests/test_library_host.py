@@ -186,3 +186,30 @@ def test_core_load_checks_the_angular_record(tmp_path):
         assert st in (_lib.WEFQ_OK, _lib.WEFQ_EHIP), L_.wefq_last_error()
         if st == _lib.WEFQ_OK:
             L_.wefq_destroy(h)
+
+
+def test_host_tables_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The host C++ (real-Gaunt table, channels, Gauss rules) built with g++ and
+    AddressSanitizer + UndefinedBehaviorSanitizer, alone (no HIP source on the line), and run
+    over L = 0..8: no report, and the driver's exact checks hold."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no g++")
+    here = os.path.dirname(os.path.abspath(__file__))
+    csrc = os.path.join(os.path.dirname(here), "paper_2605_28475_amd", "csrc")
+    exe = str(tmp_path / "host_tables_san")
+    flags = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=all", "-pthread"]
+    res = subprocess.run([gxx] + flags + ["-I", csrc, os.path.join(here, "host_tables_driver.cpp"),
+                                          os.path.join(csrc, "host_tables.cpp"), "-o", exe],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    # the process environment is kept as it is; ASan is told not to insist on being the first
+    # library in the initial list
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    run = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert run.returncode == 0, run.stdout + run.stderr
+    assert "0 failures" in run.stdout
