@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -63,6 +64,7 @@ struct wefq_core {
   uint16_t* d_Rlo = nullptr;
   int* d_units = nullptr;              // [nunits][UNIT_STRIDE]: l1, count, q1 values
   int nunits = 0;
+  long alloc_count = 0;                // device allocations so far (failure-path test hook)
   int* d_units8 = nullptr;             // units of 8 output states (FP64 two-input tiles, H >= 8)
   int nunits8 = 0;
   int GQ = 0;                          // q1 per unit
@@ -132,11 +134,22 @@ inline size_t tile_lds_bytes(const wefq_core* h, int slots, size_t elem) {
 // Error reporting helper (thread-local message).
 void set_error(const std::string& msg);
 
+// Test hook for the failure paths: with WEFQ_TEST_FAIL_DEVICE_ALLOC=n in the environment, the
+// n-th device allocation of a handle's tables (counted from 1) and every later one fail as if
+// the device were out of memory.
+inline bool injected_alloc_failure(wefq_core* h) {
+  const char* e = std::getenv("WEFQ_TEST_FAIL_DEVICE_ALLOC");
+  if (!e) return false;
+  const long n = std::atol(e);
+  return n > 0 && ++h->alloc_count >= n;
+}
+
 // Allocate device memory recorded in the handle.
 template <typename T>
 T* dev_alloc(wefq_core* h, size_t count) {
   void* p = nullptr;
   if (count == 0) count = 1;
+  if (injected_alloc_failure(h)) return nullptr;
   if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
   h->allocations.push_back(p);
   h->device_bytes += (int64_t)(count * sizeof(T));
