@@ -184,7 +184,10 @@ class Server:
         lat = np.array([t_done[r] - trace[r][0] for r in range(len(trace))])
         end = max(t_done.values()) if t_done else 0.0
         cells = sum(t[2] for t in trace)
+        # algorithmic FLOPs served (Section 4.7 count of each request's core) over the makespan
+        flop = sum(t[2] * self.cores[t[1]].info["flop_alg_per_cell"] for t in trace)
         res = {"requests": len(trace), "cells": int(cells), "launches": launches,
+               "flop_alg": float(flop), "achieved_tflops": float(flop / end / 1e12) if end > 0 else 0.0,
                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                "mean_ms": float(lat.mean() * 1e3), "max_ms": float(lat.max() * 1e3),
                "makespan_s": float(end), "throughput_cells_per_s": float(cells / end) if end > 0 else 0.0,
@@ -238,6 +241,10 @@ def bench(args):
            "config": {"workload": cfg["name"], "rate_req_per_s": cfg["rate"], "sizes": list(cfg["sizes"]),
                       "cells_per_request": "log-uniform 1..4096", "model": "hard spheres"},
            "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"], "throughput_cells_per_s": main["throughput_cells_per_s"],
+           # algorithmic FLOPs of the served requests over the makespan, against the dense FP32
+           # MFMA peak of 157.3 TFLOP/s; arrivals, not the device, bound it below saturation
+           "roofline": {"bound": "mfma", "achieved": main["achieved_tflops"], "peak": 157.3, "unit": "TFLOP/s",
+                        "frac": main["achieved_tflops"] / 157.3, "traffic": None},
            "runs": {str(int(r)): {k: v for k, v in res.items()} for r, res in runs.items()},
            "sustainable_rate_req_per_s": sustainable,
            "sustainable_rule": "highest tested rate whose run ends within 0.25 s of its trace, with p99 < 250 ms"}
