@@ -52,7 +52,11 @@ static bool upload(wefq_core* h, T*& dst, const std::vector<T>& src, hipStream_t
   dst = dev_alloc<T>(h, src.size());
   if (!dst) { set_error("device allocation failed"); return false; }
   if (src.empty()) return true;
-  if (hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess) {
+  // The source is often a block-scoped host vector that dies right after this call, and an
+  // early return on a later failure destroys the rest: wait for the copy here, so that no
+  // source has to outlive its call (a few dozen waits at build time).
+  if (hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
     set_error("host to device copy failed");
     return false;
   }
