@@ -289,6 +289,27 @@ wefq_status wefq_rk_integrate(wefq_handle h, int32_t precision, int32_t scheme, 
                               double dt, int32_t nsteps, void* work, int64_t work_bytes, double* max_invariant,
                               void* stream);
 
+/* ---- measurement helper ---- */
+
+/* What the rate probe measures. */
+typedef enum {
+  WEFQ_PROBE_MFMA_F32 = 0,   /* matrix cores, 16x16x4 FP32 */
+  WEFQ_PROBE_MFMA_F64 = 1,   /* matrix cores, 16x16x4 FP64 */
+  WEFQ_PROBE_MFMA_BF16 = 2,  /* matrix cores, 16x16x32 BF16 with FP32 accumulation */
+  WEFQ_PROBE_VALU_F32 = 3,   /* vector ALU, unpacked FP32 fused multiply-add */
+  WEFQ_PROBE_VALU_F64 = 4    /* vector ALU, FP64 fused multiply-add */
+} wefq_probe_kind;
+
+/* Attainable arithmetic rate of one device, measured so that a kernel's algorithmic rate can
+ * be set against a measured peak as well as the datasheet one (not part of the operator).
+ * Runs kernels of a few milliseconds that chain independent instructions of the given kind
+ * and touch memory only for one store per lane, on 8 workgroups of 256 threads per compute
+ * unit, and stores in *tflops the best of five launches in TFLOP/s (a multiply-add counts 2).
+ * It allocates and frees a small device buffer, so it is not for graph capture, and it
+ * synchronizes stream.  EINVAL for an unknown kind, a null tflops or a bad device ordinal;
+ * EHIP on a HIP failure. */
+wefq_status wefq_peak_probe(int32_t device, int32_t kind, double* tflops, void* stream);
+
 /* ---- host-only helpers (no device needed), used to test the host tables ---- */
 
 /* Real-Gaunt COO table (Table 1 order: q3 slowest, q1 fastest, 0-based).  Call

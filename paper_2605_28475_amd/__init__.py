@@ -261,6 +261,17 @@ def host_gauss(kind, n, alpha=0.0):
     return x, w
 
 
+PROBES = {"mfma_f32": _lib.PROBE_MFMA_F32, "mfma_f64": _lib.PROBE_MFMA_F64, "mfma_bf16": _lib.PROBE_MFMA_BF16,
+          "valu_f32": _lib.PROBE_VALU_F32, "valu_f64": _lib.PROBE_VALU_F64}
+
+
+def peak_probe(kind, device=0, stream=None):
+    """Measured attainable rate (TFLOP/s) of one kind of arithmetic on the device."""
+    out = ctypes.c_double()
+    _lib.check(_lib.lib().wefq_peak_probe(device, PROBES[kind], ctypes.byref(out), _stream_ptr(stream, device)))
+    return out.value
+
+
 class Plan:
     """Uneven batch in one persistent, graph-captured launch (wefq_plan_*).
 

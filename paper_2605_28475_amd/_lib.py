@@ -8,6 +8,7 @@ WEFQ_OK, WEFQ_EINVAL, WEFQ_ENOMEM, WEFQ_EHIP, WEFQ_EUNSUPPORTED, WEFQ_EBUDGET = 
 MAXWELL, HARD_SPHERE, VHS = 0, 1, 2
 FP64, FP32, BF16X3, FP64_NAIVE, PREP_BILINEAR, PREP_RADIAL = 1, 2, 4, 8, 16, 32
 RK_EULER, RK_HEUN, RK_SSP3, RK_CLASSIC4 = 1, 2, 3, 4
+PROBE_MFMA_F32, PROBE_MFMA_F64, PROBE_MFMA_BF16, PROBE_VALU_F32, PROBE_VALU_F64 = range(5)
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED", 5: "EBUDGET"}
 
@@ -93,6 +94,8 @@ _SIGNATURES = [
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                          ctypes.c_void_p]),
+    ("wefq_peak_probe", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.c_void_p]),
 ]
 
 
