@@ -99,14 +99,19 @@ static int probe_iters(int kind) {
   }
 }
 
+template <int KIND>
+static void launch_kind(int grid, double* out, int iters, float seed, hipStream_t s) {
+  hipLaunchKernelGGL(peak_kernel<KIND>, dim3(grid), dim3(kProbeBlock), 0, s, out, iters, seed);
+}
+
 static void launch_probe(int kind, int grid, double* out, int iters, hipStream_t s) {
   const float seed = 1e-3f;
   switch (kind) {
-    case WEFQ_PROBE_MFMA_F32: peak_kernel<WEFQ_PROBE_MFMA_F32><<<grid, kProbeBlock, 0, s>>>(out, iters, seed); break;
-    case WEFQ_PROBE_MFMA_F64: peak_kernel<WEFQ_PROBE_MFMA_F64><<<grid, kProbeBlock, 0, s>>>(out, iters, seed); break;
-    case WEFQ_PROBE_MFMA_BF16: peak_kernel<WEFQ_PROBE_MFMA_BF16><<<grid, kProbeBlock, 0, s>>>(out, iters, seed); break;
-    case WEFQ_PROBE_VALU_F32: peak_kernel<WEFQ_PROBE_VALU_F32><<<grid, kProbeBlock, 0, s>>>(out, iters, seed); break;
-    default: peak_kernel<WEFQ_PROBE_VALU_F64><<<grid, kProbeBlock, 0, s>>>(out, iters, seed); break;
+    case WEFQ_PROBE_MFMA_F32: launch_kind<WEFQ_PROBE_MFMA_F32>(grid, out, iters, seed, s); break;
+    case WEFQ_PROBE_MFMA_F64: launch_kind<WEFQ_PROBE_MFMA_F64>(grid, out, iters, seed, s); break;
+    case WEFQ_PROBE_MFMA_BF16: launch_kind<WEFQ_PROBE_MFMA_BF16>(grid, out, iters, seed, s); break;
+    case WEFQ_PROBE_VALU_F32: launch_kind<WEFQ_PROBE_VALU_F32>(grid, out, iters, seed, s); break;
+    default: launch_kind<WEFQ_PROBE_VALU_F64>(grid, out, iters, seed, s); break;
   }
 }
 
