@@ -221,7 +221,7 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   if (slots == 0) return hipErrorInvalidValue;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
-  p.nsplit = tile_splits(h, ntiles);
+  p.nsplit = tile_splits(h, ntiles, p.nunits);
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   switch (h->H) {
     case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);

@@ -65,7 +65,7 @@ struct wefq_core {
   int* d_units = nullptr;              // [nunits][UNIT_STRIDE]: l1, count, q1 values
   int nunits = 0;
   long alloc_count = 0;                // device allocations so far (failure-path test hook)
-  int* d_units8 = nullptr;             // units of 8 output states (FP64 two-input tiles, H >= 8)
+  int* d_units8 = nullptr;             // units of 8 output states (FP64 two-input tiles, H >= 7)
   int nunits8 = 0;
   int GQ = 0;                          // q1 per unit
   double tile_cost = 0.0;              // estimated cost of one full 16-cell tile (scheduling only)
@@ -105,17 +105,17 @@ __host__ __device__ inline int tile_upper_row(int NK, int H, int TB) {
   return tile_upper_k(NK, H) + tile_pad_rows(NK, H, TB);
 }
 
-// Workgroups per cell tile for a launch of ntiles tiles: small batches split each tile's
-// work units over several workgroups, so that the launch still covers about one
-// workgroup per compute unit (latency mode); every workgroup keeps at least 4 units
-// for its 8 waves.  (Measured at K = L = 8, 12 and 16: a second split workgroup per
+// Workgroups per cell tile for a launch of ntiles tiles over a list of nunits work units:
+// small batches split each tile's units over several workgroups, so that the launch still
+// covers about one workgroup per compute unit (latency mode); every workgroup keeps at
+// least 4 units for its 8 waves.  (Measured at K = L = 8, 12 and 16: a second split workgroup per
 // compute unit costs more than it hides, since the tile fills the LDS at K >= 12 and
 // 8 waves keep the CU busy at K = 8.)
-inline int tile_splits(const wefq_core* h, int64_t ntiles) {
+inline int tile_splits(const wefq_core* h, int64_t ntiles, int nunits) {
   const int64_t target = (int64_t)h->cu_count;
   if (ntiles <= 0 || ntiles >= target) return 1;
   const int64_t want = (target + ntiles - 1) / ntiles;
-  const int64_t cap = h->nunits / 4 > 1 ? h->nunits / 4 : 1;
+  const int64_t cap = nunits / 4 > 1 ? nunits / 4 : 1;
   return (int)(want < cap ? want : cap);
 }
 
