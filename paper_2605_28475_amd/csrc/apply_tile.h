@@ -41,8 +41,8 @@ struct MfmaParams {
   const double* R16_64;
 };
 
-// output states per work unit (fewer for 8x8 and 9x9 quadrants, where registers are scarce)
-__host__ __device__ constexpr int gq_for(int H) { return H >= 8 ? 4 : 8; }
+// output states per work unit (the same for every quadrant size)
+__host__ __device__ constexpr int gq_for(int) { return kUnitStates; }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 

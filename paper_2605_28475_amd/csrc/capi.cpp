@@ -380,16 +380,14 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     }
     return (int)units.size();
   };
-  // The kernels take up to gq_for(H) output states per unit (8 for quadrants up to 7x7, 4
-  // above).  Units hold at most 4: a wave then runs a shorter serial chain, and the units of
-  // a tile balance better over its 8 waves.  Against units of 8 this measured 5-45% faster
-  // for K <= 8 at every batch size from 256 to 65,536 cells, up to 47% faster at K = 10
-  // and 12 below 4,096 cells, and equal at K = 10 and 12 on larger batches; results are
-  // bitwise the same.
-  h->GQ = H >= 8 ? 4 : 8;     // the kernels' capacity per unit (gq_for)
-  constexpr int kUnitStates = 4;
+  // Units hold kUnitStates = 4 output states: a wave then runs a shorter serial chain, and
+  // the units of a tile balance better over its 8 waves.  Against units of 8 this measured
+  // 5-45% faster for K <= 8 at every batch size from 256 to 65,536 cells, up to 47% faster
+  // at K = 10 and 12 below 4,096 cells, and equal at K = 10 and 12 on larger batches;
+  // results are bitwise the same.
+  h->GQ = kUnitStates;
   std::vector<int> uarr;
-  h->nunits = build_units(kUnitStates, uarr, h->tile_cost);
+  h->nunits = build_units(h->GQ, uarr, h->tile_cost);
   // the FP64 two-input tiles of 2 cells carry 8 output states per column group (H >= 7):
   // they get units of 8
   if (H >= 7 && want64) {

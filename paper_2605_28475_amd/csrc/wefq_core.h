@@ -105,6 +105,12 @@ __host__ __device__ inline int tile_upper_row(int NK, int H, int TB) {
   return tile_upper_k(NK, H) + tile_pad_rows(NK, H, TB);
 }
 
+// Output states per work unit, for every quadrant size.  Units of 4 states give each wave
+// shorter serial chains than 8 and balance a tile's waves better; the kernels then hold 4
+// accumulator groups instead of 8, which was faster again in FP64 (5% at K = L = 12) and at
+// small truncations.  Tiles with 8 output states per column group take units of 8.
+constexpr int kUnitStates = 4;
+
 // Workgroups per cell tile for a launch of ntiles tiles over a list of nunits work units:
 // small batches split each tile's units over several workgroups, so that the launch still
 // covers about one workgroup per compute unit (latency mode); every workgroup keeps at
