@@ -119,57 +119,73 @@ static hipError_t launch_mfma_t(const MfmaParams& p, int64_t ntiles, int block, 
 }
 
 template <int H, int SLOTS, int RT, int MODE>
-static int spill_t() {
-  hipFuncAttributes a;
-  if (hipFuncGetAttributes(&a, (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE>) != hipSuccess) return -1;
-  return (int)a.localSizeBytes;
+static const void* kernel_t() {
+  return (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE>;
 }
 
-// One instance per (H, slots, RT, mode), chosen at run time; every dispatcher below
-// goes through this switch so that the launch and the spill query see the same kernels.
+// One instance per (H, slots, RT, mode), chosen at run time; the launch dispatch below and
+// the attribute queries (spills, residency) see the same kernels.
 template <int H, int RT, int MODE>
-static int spill_s(int slots) {
+static const void* kernel_s(int slots) {
   switch (slots) {
-    case 1: return spill_t<H, 1, RT, MODE>();
-    case 2: return spill_t<H, 2, RT, MODE>();
-    case 4: return spill_t<H, 4, RT, MODE>();
-    default: return -1;
+    case 1: return kernel_t<H, 1, RT, MODE>();
+    case 2: return kernel_t<H, 2, RT, MODE>();
+    case 4: return kernel_t<H, 4, RT, MODE>();
+    default: return nullptr;
   }
 }
 
 template <int H>
-static int spill_h(int mode, int slots, int rt) {
+static const void* kernel_h(int mode, int slots, int rt) {
   if (rt == 2) {
     if constexpr (H >= 8) {
       switch (mode) {
-        case 0: return spill_s<H, 2, 0>(slots);
-        case 1: return spill_s<H, 2, 1>(slots);
-        case 2: return spill_s<H, 2, 2>(slots);
+        case 0: return kernel_s<H, 2, 0>(slots);
+        case 1: return kernel_s<H, 2, 1>(slots);
+        case 2: return kernel_s<H, 2, 2>(slots);
       }
     }
-    return -1;
+    return nullptr;
   }
   switch (mode) {
-    case 0: return spill_s<H, 1, 0>(slots);
-    case 1: return spill_s<H, 1, 1>(slots);
-    case 2: return spill_s<H, 1, 2>(slots);
+    case 0: return kernel_s<H, 1, 0>(slots);
+    case 1: return kernel_s<H, 1, 1>(slots);
+    case 2: return kernel_s<H, 1, 2>(slots);
   }
-  return -1;
+  return nullptr;
+}
+
+static const void* mfma_kernel(const wefq_core* h, int mode, int slots) {
+  switch (h->H) {
+    case 1: return kernel_h<1>(mode, slots, h->RT);
+    case 2: return kernel_h<2>(mode, slots, h->RT);
+    case 3: return kernel_h<3>(mode, slots, h->RT);
+    case 4: return kernel_h<4>(mode, slots, h->RT);
+    case 5: return kernel_h<5>(mode, slots, h->RT);
+    case 6: return kernel_h<6>(mode, slots, h->RT);
+    case 7: return kernel_h<7>(mode, slots, h->RT);
+    case 8: return kernel_h<8>(mode, slots, h->RT);
+    case 9: return kernel_h<9>(mode, slots, h->RT);
+    default: return nullptr;
+  }
 }
 
 int mfma_spill_bytes(const wefq_core* h, int mode, int slots) {
-  switch (h->H) {
-    case 1: return spill_h<1>(mode, slots, h->RT);
-    case 2: return spill_h<2>(mode, slots, h->RT);
-    case 3: return spill_h<3>(mode, slots, h->RT);
-    case 4: return spill_h<4>(mode, slots, h->RT);
-    case 5: return spill_h<5>(mode, slots, h->RT);
-    case 6: return spill_h<6>(mode, slots, h->RT);
-    case 7: return spill_h<7>(mode, slots, h->RT);
-    case 8: return spill_h<8>(mode, slots, h->RT);
-    case 9: return spill_h<9>(mode, slots, h->RT);
-    default: return -1;
-  }
+  const void* k = mfma_kernel(h, mode, slots);
+  hipFuncAttributes a;
+  if (!k || hipFuncGetAttributes(&a, k) != hipSuccess) return -1;
+  return (int)a.localSizeBytes;
+}
+
+int mfma_blocks_per_cu(const wefq_core* h, int mode, int slots, int block) {
+  const void* k = mfma_kernel(h, mode, slots);
+  if (!k) return 0;
+  const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
+  int n = 0;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds) != hipSuccess)
+    return 0;
+  return n;
 }
 
 template <int H, int RT, int MODE>
@@ -221,7 +237,7 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   if (slots == 0) return hipErrorInvalidValue;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
-  p.nsplit = tile_splits(h, ntiles, p.nunits);
+  p.nsplit = tile_splits(h, ntiles, p.nunits, h->split_per_cu[mode]);
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   switch (h->H) {
     case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);

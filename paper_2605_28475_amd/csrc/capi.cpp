@@ -63,6 +63,18 @@ static bool upload(wefq_core* h, T*& dst, const std::vector<T>& src, hipStream_t
   return true;
 }
 
+// Split workgroups per compute unit for small batches (tile_splits): 2 where two workgroups
+// of the mode's kernel fit on a compute unit at its tile shape and its quadrants are 4x4 or
+// larger, else 1.  A second resident workgroup doubles the waves that hide the coupling's
+// latency, at the price of staging each tile twice; measured at 4,096 cells it gained 14-15%
+// at K = L = 8 and 2-7% at K = L = 6 (FP32, BF16x3) and lost 10-33% at K = L = 4, whose
+// tiles are too small to repay the staging; where two do not fit (FP64 from 4x4 quadrants
+// up, every precision from K = L = 10) the second workgroup only queues, and lost up to 70%.
+static int split_target(const wefq_core* h, int mode) {
+  if (h->slots[mode] == 0 || h->H < 4) return 1;
+  return mfma_blocks_per_cu(h, mode, h->slots[mode], h->block[mode]) >= 2 ? 2 : 1;
+}
+
 bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t s) {
   const int NK = h->NK, NQ = h->NQ, L = h->L;
   const size_t blk = (size_t)NK * NK * NK;
@@ -263,6 +275,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   for (int mode = 0; mode < 3; ++mode) {
     h->slots[mode] = pick_slots(mode);
     h->block[mode] = 512;
+    h->split_per_cu[mode] = split_target(h, mode);
   }
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;   // RT == 2: NK = 17
   // A-operand value for lane group r at step t: the group's quadrant starts at k = 0
@@ -772,6 +785,7 @@ wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32
     return fail(WEFQ_EUNSUPPORTED, "tile of 16/slots cells does not fit in LDS");
   h->slots[mode] = slots;
   h->block[mode] = block;
+  h->split_per_cu[mode] = split_target(h, mode);
   return WEFQ_OK;
 }
 

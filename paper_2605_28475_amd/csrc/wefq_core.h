@@ -44,6 +44,7 @@ struct wefq_core {
   int H = 0, RT = 0;                   // quadrant size; RT == 2 marks NK = 17 (row 16 on the VALU)
   int slots[3] = {0, 0, 0};            // tile shape per mode (0 FP32, 1 BF16X3, 2 FP64): the cell
   int block[3] = {512, 512, 512};      // tile is 16/slots cells; block = threads per workgroup
+  int split_per_cu[3] = {1, 1, 1};     // split workgroups per compute unit for small batches
   int* d_chan_begin = nullptr;         // L + 2: merged channels of l1 are [begin[l1], begin[l1+1])
   int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
@@ -114,11 +115,14 @@ constexpr int kUnitStates = 4;
 // Workgroups per cell tile for a launch of ntiles tiles over a list of nunits work units:
 // small batches split each tile's units over several workgroups, so that the launch still
 // covers about one workgroup per compute unit (latency mode); every workgroup keeps at
-// least 4 units for its 8 waves.  (Measured at K = L = 8, 12 and 16: a second split workgroup per
-// compute unit costs more than it hides, since the tile fills the LDS at K >= 12 and
-// 8 waves keep the CU busy at K = 8.)
-inline int tile_splits(const wefq_core* h, int64_t ntiles, int nunits) {
-  const int64_t target = (int64_t)h->cu_count;
+// least 4 units for its 8 waves.  per_cu is 2 where two workgroups of the kernel fit on a
+// compute unit and its quadrants are 4x4 or larger (set at core build), else 1: a launch of
+// one to per_cu tiles per compute unit then splits its tiles to about per_cu workgroups per
+// compute unit.  (Below one tile per compute unit the units per workgroup run short of its
+// 8 waves first: at K = L = 8 with 1,024 cells, targeting two per unit cost 17%.)
+inline int tile_splits(const wefq_core* h, int64_t ntiles, int nunits, int per_cu) {
+  const int64_t cus = (int64_t)h->cu_count;
+  const int64_t target = (per_cu > 1 && ntiles >= cus) ? cus * per_cu : cus;
   if (ntiles <= 0 || ntiles >= target) return 1;
   const int64_t want = (target + ntiles - 1) / ntiles;
   const int64_t cap = nunits / 4 > 1 ? nunits / 4 : 1;
@@ -177,6 +181,9 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
 // Private (scratch) bytes per lane of the MFMA kernel instance of a tile shape:
 // nonzero when it spills registers.  Returns -1 for a shape with no instance.
 int mfma_spill_bytes(const wefq_core* h, int mode, int slots);
+// Workgroups of the apply kernel for (mode, slots) resident per compute unit at the given
+// block size with its LDS tile; 0 when the query fails.
+int mfma_blocks_per_cu(const wefq_core* h, int mode, int slots, int block);
 // Jacobian-vector product out = J(c) d = Q(c, d) + Q(d, c) for FP32 or FP64 (jvp.hip).
 hipError_t launch_apply_jvp(const wefq_core* h, int precision, const void* c, const void* d, void* out,
                             int64_t B, int64_t ldc, int64_t ldd, int64_t ldo, hipStream_t s);
