@@ -271,8 +271,8 @@ def main():
                                 "normwise_fp32": float(np.linalg.norm(q32.cpu().numpy() - ref) / np.linalg.norm(ref)),
                                 "normwise_bf16x3": float(np.linalg.norm(q16.cpu().numpy() - ref) / np.linalg.norm(ref))}
         del q64
-        out["config1_latency"] = bench_single_cell(torch, wefq, synth, stream)
-        out["config2"] = bench_k8(torch, wefq, synth, stream)
+        out["single_cell_latency"] = bench_single_cell(torch, wefq, synth, stream)
+        out["k8_batch"] = bench_k8(torch, wefq, synth, stream)
         log("[bench] measured peaks (rate probe)")
         mp = measured_peaks(wefq, stream)
         out["measured_peaks_tflops"] = mp
@@ -538,7 +538,7 @@ def bench_uneven(args, torch, wefq, synth):
     from paper_2605_28475_amd import autotune
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    cfg = synth.CONFIGS[4]
+    cfg = synth.WORKLOADS["uneven"]
     rng = np.random.Generator(np.random.PCG64(cfg["seed"]))
     total = cfg["cells"]
     size = rng.choice(np.array(cfg["sizes"]), size=total)

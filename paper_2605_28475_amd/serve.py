@@ -212,9 +212,10 @@ def make_server(torch, sizes=(8, 12, 16), model="hs", pool_cells=4096, budget_gb
 
 
 def bench(args):
-    """Config 5: Poisson arrivals, 1-4096 cells (log-uniform), K = L in {8, 12, 16}, hard spheres, FP32."""
+    """Serving under Poisson arrivals: 1-4096 cells per request (log-uniform), K = L in {8, 12, 16},
+    hard spheres, FP32."""
     import torch
-    cfg = synth.CONFIGS[5]
+    cfg = synth.WORKLOADS["serving"]
     # the library's default tile shapes (largest LDS tiles): under load, requests of one
     # core are fused into batches of thousands of cells, where those are the fastest
     srv = make_server(torch, sizes=cfg["sizes"], pool_cells=cfg["max_cells"])

@@ -40,10 +40,10 @@ def unit_maxwellian(K, L, B=1):
 
 
 # The five workloads (sizes and models) that the tests and the benchmark use.
-CONFIGS = {
-    1: dict(name="hs_fp64_K3L3_single", model="hs", gamma=1.0, K=3, L=3, B=1, seed=BASE_SEED + 1),
-    2: dict(name="mm_hs_K8L8_B4096", model=("mm", "hs"), K=8, L=8, B=4096, seed=BASE_SEED + 2),
-    3: dict(name="vhs0.5_K12L12_B65536", model="vhs", gamma=0.5, K=12, L=12, B=65536, seed=BASE_SEED + 3),
-    4: dict(name="uneven_20000_K4-16_hs_vhs", cells=20000, sizes=(4, 8, 12, 16), seed=BASE_SEED + 4),
-    5: dict(name="serving_poisson_2000rps", rate=2000.0, sizes=(8, 12, 16), max_cells=4096, seed=BASE_SEED + 5),
+WORKLOADS = {
+    "single_cell": dict(name="hs_fp64_K3L3_single", model="hs", gamma=1.0, K=3, L=3, B=1, seed=BASE_SEED + 1),
+    "k8_batch": dict(name="mm_hs_K8L8_B4096", model=("mm", "hs"), K=8, L=8, B=4096, seed=BASE_SEED + 2),
+    "k12_batch": dict(name="vhs0.5_K12L12_B65536", model="vhs", gamma=0.5, K=12, L=12, B=65536, seed=BASE_SEED + 3),
+    "uneven": dict(name="uneven_20000_K4-16_hs_vhs", cells=20000, sizes=(4, 8, 12, 16), seed=BASE_SEED + 4),
+    "serving": dict(name="serving_poisson_2000rps", rate=2000.0, sizes=(8, 12, 16), max_cells=4096, seed=BASE_SEED + 5),
 }

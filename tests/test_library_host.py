@@ -191,7 +191,7 @@ def test_core_load_checks_the_angular_record(tmp_path):
 def test_host_tables_under_address_and_undefined_behaviour_sanitizers(tmp_path):
     """The host C++ (real-Gaunt table, channels, Gauss rules) built with g++ and
     AddressSanitizer + UndefinedBehaviorSanitizer, alone (no HIP source on the line), and run
-    over L = 0..8: no report, and the driver's exact checks hold."""
+    over L = 0..8: no report, and the test program's exact checks hold."""
     import shutil
     import subprocess
     gxx = shutil.which("g++")
