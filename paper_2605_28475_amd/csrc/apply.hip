@@ -237,7 +237,8 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   if (slots == 0) return hipErrorInvalidValue;
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
-  p.nsplit = tile_splits(h, ntiles, p.nunits, h->split_per_cu[mode]);
+  p.nsplit = tile_splits(h, ntiles, p.nunits, h->split_per_cu[mode],
+                         (int64_t)h->cu_count * h->resident_per_cu[mode]);
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   switch (h->H) {
     case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);

@@ -75,6 +75,13 @@ static int split_target(const wefq_core* h, int mode) {
   return mfma_blocks_per_cu(h, mode, h->slots[mode], h->block[mode]) >= 2 ? 2 : 1;
 }
 
+// Workgroups of the mode's kernel resident per compute unit at its tile shape (at least 1).
+static int resident_blocks(const wefq_core* h, int mode) {
+  if (h->slots[mode] == 0) return 1;
+  const int n = mfma_blocks_per_cu(h, mode, h->slots[mode], h->block[mode]);
+  return n > 1 ? n : 1;
+}
+
 bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t s) {
   const int NK = h->NK, NQ = h->NQ, L = h->L;
   const size_t blk = (size_t)NK * NK * NK;
@@ -276,6 +283,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     h->slots[mode] = pick_slots(mode);
     h->block[mode] = 512;
     h->split_per_cu[mode] = split_target(h, mode);
+    h->resident_per_cu[mode] = resident_blocks(h, mode);
   }
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;   // RT == 2: NK = 17
   // A-operand value for lane group r at step t: the group's quadrant starts at k = 0
@@ -786,6 +794,7 @@ wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32
   h->slots[mode] = slots;
   h->block[mode] = block;
   h->split_per_cu[mode] = split_target(h, mode);
+  h->resident_per_cu[mode] = resident_blocks(h, mode);
   return WEFQ_OK;
 }
 

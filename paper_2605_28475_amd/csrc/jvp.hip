@@ -91,7 +91,7 @@ static hipError_t launch_two(const wefq_core* h, bool anti, int precision, const
   if (slots == 8 && h->d_units8) { p.units = h->d_units8; p.nunits = h->nunits8; }
   const int TB = 16 / slots;
   const int64_t ntiles = (B + TB - 1) / TB;
-  p.nsplit = tile_splits(h, ntiles, p.nunits, 1);
+  p.nsplit = tile_splits(h, ntiles, p.nunits, 1, 0);
   if (p.nsplit > 1 && p.nsplit > p.nunits / 4) p.nsplit = p.nunits / 4 > 1 ? p.nunits / 4 : 1;
   const size_t lds = 2 * tile_lds_bytes(h, slots, elem);
   switch (h->H) {
