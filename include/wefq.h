@@ -219,6 +219,10 @@ const char* wefq_last_error(void);
  * bitwise independent of the shape.  The default, set by wefq_build_core, is the
  * largest tile that fits in LDS with a kernel that spills at most 128 bytes of
  * registers per lane, at 512 threads; the autotuner may replace it.  Each precision keeps its own shape.
+ * Setting a shape also re-derives how small batches split their tiles over workgroups
+ * (a residency query of the kernel on the core's device, which the call makes current).
+ * EINVAL for an unknown precision, slots or block; EUNSUPPORTED when the tile does not
+ * fit in LDS; EHIP when the device cannot be selected.
  * Not thread-safe with concurrent applies of the same core. */
 wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32_t block);
 /* The shape wefq_apply_Q currently uses for a precision.  EINVAL for a null argument or a

@@ -791,6 +791,8 @@ wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32
   const size_t elem = mode == 2 ? 8 : 4;
   if (tile_lds_bytes(h, slots, elem) > (size_t)h->lds_limit)
     return fail(WEFQ_EUNSUPPORTED, "tile of 16/slots cells does not fit in LDS");
+  // the residency queries below run on the current device
+  if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
   h->slots[mode] = slots;
   h->block[mode] = block;
   h->split_per_cu[mode] = split_target(h, mode);
