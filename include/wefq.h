@@ -218,7 +218,8 @@ const char* wefq_last_error(void);
  * and must fit in LDS), block = threads per workgroup (256 or 512).  Results are
  * bitwise independent of the shape.  The default, set by wefq_build_core, is the
  * largest tile that fits in LDS with a kernel that spills at most 128 bytes of
- * registers per lane, at 512 threads; the autotuner may replace it.  Each precision keeps its own shape.
+ * registers per lane, at 512 threads (256 when a tile holds fewer than 16 work units of up
+ * to 4 output states each); the autotuner may replace it.  Each precision keeps its own shape.
  * Setting a shape also re-derives how small batches split their tiles over workgroups
  * (a residency query of the kernel on the core's device, which the call makes current).
  * EINVAL for an unknown precision, slots or block; EUNSUPPORTED when the tile does not

@@ -279,12 +279,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     }
     return first_fit;
   };
-  for (int mode = 0; mode < 3; ++mode) {
-    h->slots[mode] = pick_slots(mode);
-    h->block[mode] = 512;
-    h->split_per_cu[mode] = split_target(h, mode);
-    h->resident_per_cu[mode] = resident_blocks(h, mode);
-  }
+  for (int mode = 0; mode < 3; ++mode) h->slots[mode] = pick_slots(mode);
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;   // RT == 2: NK = 17
   // A-operand value for lane group r at step t: the group's quadrant starts at k = 0
   // (lower half) or k = tile_upper_k (upper half); upper-half rows outside [H, NK), the
@@ -409,6 +404,15 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   h->GQ = kUnitStates;
   std::vector<int> uarr;
   h->nunits = build_units(h->GQ, uarr, h->tile_cost);
+  // Default block: 512 threads, or 256 when a tile holds fewer than 16 work units, too few to
+  // keep 8 waves busy.  Measured with 9 to 12 units (K = L = 4 and 5; K = 8, 12, 16 at
+  // L = 2 to 4): 256 threads were 1-33% faster in 18 of 20 cases and 2% slower in 2; with 16
+  // units (K = L = 6) it was mixed, with 57 (K = 4, L = 13) 1.5-1.9x slower.
+  for (int mode = 0; mode < 3; ++mode) {
+    h->block[mode] = h->nunits < 16 ? 256 : 512;
+    h->split_per_cu[mode] = split_target(h, mode);
+    h->resident_per_cu[mode] = resident_blocks(h, mode);
+  }
   // the FP64 two-input tiles of 2 cells carry 8 output states per column group (H >= 7):
   // they get units of 8
   if (H >= 7 && want64) {
