@@ -74,38 +74,54 @@ def time_steps(fn, steps, stream, torch):
 
 def _oracle_cells(job):
     """The oracle's literal factorized sum (Section 4.5 as written) over cells until the time
-    budget runs out, with one BLAS thread; returns (cells done, seconds)."""
+    budget runs out, with one BLAS thread; returns (cells done, seconds, their Q rows)."""
     R, T, K, cells, budget = job
     from threadpoolctl import threadpool_limits
     from oracle import apply as oapply
+    out = []
     with threadpool_limits(limits=1):
         done, t0 = 0, time.perf_counter()
         while done < len(cells) and time.perf_counter() - t0 < budget:
-            oapply.apply_q(R, T, cells[done], K)
+            out.append(oapply.apply_q(R, T, cells[done], K))
             done += 1
-        return done, time.perf_counter() - t0
+        return done, time.perf_counter() - t0, np.array(out).reshape(done, -1)
 
 
 def cpu_baseline(K, L, gamma, c, budget_s, single_budget_s=5.0, max_workers=16):
     """The oracle on the host: one worker process per core (at most max_workers), each on its
     own cells of the batch for budget_s, and one thread alone for single_budget_s.  Runs
-    before the GPU is initialized, so the workers are plain CPU processes."""
+    before the GPU is initialized, so the workers are plain CPU processes.  Returns the
+    record and the oracle's Q for the cells it finished (batch indices, rows), which the GPU
+    results are then checked against."""
     import multiprocessing
     from oracle import core as ocore, gaunt as ogaunt
     T = ogaunt.coo(L)
     R = ocore.zero_invariants(ocore.core_exact(K, L, gamma, table=T), T["channels"])
-    done1, dt1 = _oracle_cells((R, T, K, c[:64], single_budget_s))
+    done1, dt1, _ = _oracle_cells((R, T, K, c[:64], single_budget_s))
     workers = max(1, min(os.cpu_count() or 1, max_workers))
     cap = min(len(c), 256 * workers)
     jobs = [(R, T, K, np.ascontiguousarray(c[i:cap:workers]), budget_s) for i in range(workers)]
     with multiprocessing.get_context("spawn").Pool(workers) as pool:
         res = pool.map(_oracle_cells, jobs)
     done, dt = sum(r[0] for r in res), max(r[1] for r in res)
-    return {"value": done / dt, "unit": "cells/s", "cores": workers, "kind": "oracle",
-            "sample": f"{done} cells of the same batch over {workers} worker processes with one thread each "
-                      f"(oracle factorized sum, Section 4.5 as written), {dt:.1f} s",
-            "single_thread": {"value": done1 / dt1, "unit": "cells/s", "cores": 1,
-                              "sample": f"{done1} cells, {dt1:.1f} s"}}
+    idx = np.concatenate([np.arange(i, cap, workers)[:r[0]] for i, r in enumerate(res)])
+    qref = np.concatenate([r[2] for r in res])
+    rec = {"value": done / dt, "unit": "cells/s", "cores": workers, "kind": "oracle",
+           "sample": f"{done} cells of the same batch over {workers} worker processes with one thread each "
+                     f"(oracle factorized sum, Section 4.5 as written), {dt:.1f} s",
+           "single_thread": {"value": done1 / dt1, "unit": "cells/s", "cores": 1,
+                             "sample": f"{done1} cells, {dt1:.1f} s"}}
+    return rec, (idx, qref)
+
+
+def mode_errors(q, ref):
+    """Error per output mode alpha, e_alpha = max_b |q_b,alpha - ref_b,alpha| / max_{b,alpha'} |ref|,
+    summarized as its maximum and median over modes, and the normwise relative error."""
+    q = np.asarray(q, dtype=np.float64)
+    scale = np.abs(ref).max()
+    e = np.abs(q - ref).max(axis=0) / scale
+    return {"max_mode": float(e.max()), "median_mode": float(np.median(e)),
+            "normwise": float(np.linalg.norm(q - ref) / np.linalg.norm(ref))}
 
 
 def host_cpu_model():
@@ -175,10 +191,10 @@ def main():
     K, L, B, gamma = args.K, args.L, args.cells, args.gamma
     workload = f"vhs{gamma:g}_K{K}L{L}_B{B}"
     c = synth.perturbed_maxwellian(K, L, B, seed=synth.BASE_SEED + 3)
-    cpu = None
+    cpu = oracle_q = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle), before the GPU is initialized")
-        cpu = cpu_baseline(K, L, gamma, c, args.cpu_budget)
+        cpu, oracle_q = cpu_baseline(K, L, gamma, c, args.cpu_budget)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
@@ -251,25 +267,33 @@ def main():
         core.apply_Q(f32, out=q32)
         torch.cuda.synchronize()
         ref = q64.cpu().numpy()
-        scale = np.abs(ref).max()
-        err32 = np.abs(q32.cpu().numpy() - ref).max(axis=0) / scale
-        err16 = np.abs(q16.cpu().numpy() - ref).max(axis=0) / scale
-        out["fp64_plain"] = {"cells_per_s": B / (np.mean(ms64) * 1e-3), "kernel_ms": float(np.mean(ms64)),
+        h32, h16 = q32.cpu().numpy(), q16.cpu().numpy()
+        fp64_naive_cps = nb / (np.mean(msn) * 1e-3)
+        out["fp64_tiled"] = {"cells_per_s": B / (np.mean(ms64) * 1e-3), "kernel_ms": float(np.mean(ms64)),
                              "roofline_frac": flop_cell * B / (np.mean(ms64) * 1e-3) / 1e12 / PEAK["fp64"],
-                             "kernel": "angular-first tiles, FP64 coupling + FP64 MFMA"}
-        out["fp64_naive"] = {"cells_per_s": nb / (np.mean(msn) * 1e-3), "cells": nb,
-                             "kernel": "naive ordering of the factorized sum, FP64, one thread per output",
-                             "max_rel_diff_vs_fp64": naive_err}
-        out["speedup_fp32_vs_fp64_naive"] = float((B / np.mean(kms)) / (nb / np.mean(msn)))
+                             "kernel": "angular-first tiles, FP64 coupling + FP64 MFMA (the same kernel as "
+                                       "the FP32 path, in FP64)"}
+        out["fp64_naive"] = {"cells_per_s": fp64_naive_cps, "cells": nb,
+                             "kernel": "plain FP64 GPU apply: the naive ordering of the factorized sum "
+                                       "(every COO row contracts its K^3 block), one thread per output",
+                             "max_rel_diff_vs_fp64_tiled": naive_err}
+        # the metric's comparator, the plain FP64 GPU apply, is the naive ordering; the tiled
+        # FP64 kernel is the same optimized kernel as the headline, in FP64
+        out["speedup_fp32_vs_fp64_naive"] = float(value / fp64_naive_cps)
+        out["speedup_fp32_vs_fp64_tiled"] = float(np.mean(ms64) / np.mean(kms))
         out["bf16x3"] = {"cells_per_s": B / (np.mean(ms16) * 1e-3), "kernel_ms": float(np.mean(ms16)),
                          # algorithmic rate; no single peak bounds it (BF16 MFMA contraction, FP32 VALU coupling)
                          "achieved_tflops_alg": flop_cell * B / (np.mean(ms16) * 1e-3) / 1e12,
                          "p50_ms": float(np.percentile(ms16, 50)), "p99_ms": float(np.percentile(ms16, 99))}
-        out["speedup_fp32_vs_fp64_plain"] = float(np.mean(ms64) / np.mean(kms))
-        out["error_vs_fp64"] = {"fp32_max_mode": float(err32.max()), "fp32_median_mode": float(np.median(err32)),
-                                "bf16x3_max_mode": float(err16.max()), "bf16x3_median_mode": float(np.median(err16)),
-                                "normwise_fp32": float(np.linalg.norm(q32.cpu().numpy() - ref) / np.linalg.norm(ref)),
-                                "normwise_bf16x3": float(np.linalg.norm(q16.cpu().numpy() - ref) / np.linalg.norm(ref))}
+        # accuracy: per output mode against the FP64 CPU oracle on the cells the CPU leg finished,
+        # and against the GPU FP64 tiled apply on every cell of the batch
+        if oracle_q is not None:
+            idx, qo = oracle_q
+            out["error_vs_oracle"] = {"cells": int(len(idx)), "reference": "FP64 CPU oracle (factorized sum "
+                                      "with the oracle's own core) on the cells of the cpu_baseline leg",
+                                      "fp32": mode_errors(h32[idx], qo), "bf16x3": mode_errors(h16[idx], qo),
+                                      "fp64_tiled": mode_errors(ref[idx], qo)}
+        out["error_vs_fp64_tiled"] = {"cells": B, "fp32": mode_errors(h32, ref), "bf16x3": mode_errors(h16, ref)}
         del q64
         out["single_cell_latency"] = bench_single_cell(torch, wefq, synth, stream)
         out["k8_batch"] = bench_k8(torch, wefq, synth, stream)
@@ -278,7 +302,7 @@ def main():
         out["measured_peaks_tflops"] = mp
         out["roofline"]["measured_peak"] = mp["mfma_f32"]
         out["roofline"]["frac_measured_peak"] = achieved / mp["mfma_f32"]
-        out["fp64_plain"]["roofline_frac_measured_peak"] = out["fp64_plain"]["roofline_frac"] * PEAK["fp64"] / mp["mfma_f64"]
+        out["fp64_tiled"]["roofline_frac_measured_peak"] = out["fp64_tiled"]["roofline_frac"] * PEAK["fp64"] / mp["mfma_f64"]
     if cpu is not None:
         out["cpu_baseline"] = cpu
     out["host_cpu"] = {"cpu_count": os.cpu_count(), "model": host_cpu_model()}

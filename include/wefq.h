@@ -147,8 +147,10 @@ wefq_status wefq_core_load(const char* path, uint32_t precisions, int32_t device
  * double for WEFQ_FP64 / WEFQ_FP64_NAIVE and float otherwise, aligned to the
  * element size, not aliasing.  Requesting WEFQ_FP64_NAIVE needs the WEFQ_FP64 tables.
  * Q is overwritten (not accumulated).  B == 0 is a no-op.  Asynchronous on
- * stream; allocates nothing.  The mass, momentum and energy rows of Q are
- * exactly 0 for every precision.  NaN/Inf in f propagate elsewhere. */
+ * stream; allocates nothing.  For finite f the mass, momentum and energy rows of Q
+ * are exactly 0 in every precision: those rows of the core are zero (Section 4.4), so
+ * every product on them is 0 x finite; they are stored as computed, not overwritten.
+ * NaN/Inf in f propagate, into those rows too. */
 wefq_status wefq_apply_Q(wefq_handle h, int32_t precision, const void* f, void* Q,
                          int64_t B, int64_t ld_f, int64_t ld_q, void* stream);
 

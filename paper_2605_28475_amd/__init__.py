@@ -24,6 +24,17 @@ def num_modes(K, L):
     return (K + 1) * (L + 1) ** 2
 
 
+def _check_tensor(name, t, want, rows, N, device=None):
+    """Refuse a tensor the library would read or write out of bounds: dtype, CUDA device,
+    unit stride in the last dimension, at least `rows` rows of exactly N modes."""
+    if t.dtype != want or t.device.type != "cuda" or (device is not None and t.device != device):
+        raise ValueError(f"{name} must be a CUDA {want} tensor on {device or 'the GPU'}")
+    if t.dim() != 2 or t.shape[1] != N or t.shape[0] < rows:
+        raise ValueError(f"{name} must have shape ({rows}, {N}); got {tuple(t.shape)}")
+    if t.stride(-1) != 1 or (t.shape[0] > 1 and t.stride(0) < N):
+        raise ValueError(f"{name} must have unit stride in the last dimension and rows at least N apart")
+
+
 def _stream_ptr(stream, device):
     import torch
     if stream is None:
@@ -106,11 +117,13 @@ class Core:
         f2 = f.unsqueeze(0) if squeeze else f
         prec = self._prec(f2, precision)
         want = torch.float64 if prec in (FP64, FP64_NAIVE) else torch.float32
-        if f2.dtype != want or f2.device.type != "cuda" or f2.stride(-1) != 1:
-            raise ValueError(f"f must be a CUDA {want} tensor with unit stride in the last dimension")
+        _check_tensor("f", f2, want, f2.shape[0], self.N)
         B = f2.shape[0]
         if out is None:
-            out = torch.empty((B, f2.shape[1]), dtype=want, device=f2.device)
+            out = torch.empty((B, self.N), dtype=want, device=f2.device)
+        else:
+            out = out.unsqueeze(0) if (squeeze and out.dim() == 1) else out
+            _check_tensor("out", out, want, B, self.N, f2.device)
         _lib.check(_lib.lib().wefq_apply_Q(self._h, prec, ctypes.c_void_p(f2.data_ptr()),
                                            ctypes.c_void_p(out.data_ptr()), B, f2.stride(0) if B > 1 else f2.shape[1],
                                            out.stride(0) if B > 1 else out.shape[1],
@@ -134,11 +147,16 @@ class Core:
         "radial").  work: a uint8 device tensor; by default one is allocated for chunks of
         `chunk` cells (default: the batch, capped so that the workspace stays under 1 GiB)."""
         import torch
-        if f.dtype != torch.float64 or f.device.type != "cuda" or f.dim() != 2 or f.stride(-1) != 1:
-            raise ValueError("f must be a CUDA float64 [B, N] tensor with unit stride in the last dimension")
+        if f.dim() != 2:
+            raise ValueError("f must be a [B, N] tensor")
         B = f.shape[0]
+        _check_tensor("f", f, torch.float64, B, self.N)
         if out is None:
-            out = torch.empty((B, f.shape[1]), dtype=torch.float64, device=f.device)
+            out = torch.empty((B, self.N), dtype=torch.float64, device=f.device)
+        else:
+            _check_tensor("out", out, torch.float64, B, self.N, f.device)
+        if work is not None and (work.device != f.device or not work.is_contiguous()):
+            raise ValueError("work must be a contiguous tensor on the device of f")
         if work is None:
             per64 = self.radial_workspace_bytes(64)
             if chunk is None:
@@ -165,14 +183,16 @@ class Core:
         d2 = d.unsqueeze(0) if d.dim() == 1 else d
         prec = self._prec(c2, precision)
         want = torch.float64 if prec == FP64 else torch.float32
-        for t in (c2, d2):
-            if t.dtype != want or t.device.type != "cuda" or t.stride(-1) != 1:
-                raise ValueError(f"c and d must be CUDA {want} tensors with unit stride in the last dimension")
+        B = c2.shape[0]
+        _check_tensor("c", c2, want, B, self.N)
+        _check_tensor("d", d2, want, B, self.N, c2.device)
         if d2.shape != c2.shape:
             raise ValueError("c and d must have the same shape")
-        B = c2.shape[0]
         if out is None:
-            out = torch.empty((B, c2.shape[1]), dtype=want, device=c2.device)
+            out = torch.empty((B, self.N), dtype=want, device=c2.device)
+        else:
+            out = out.unsqueeze(0) if (squeeze and out.dim() == 1) else out
+            _check_tensor("out", out, want, B, self.N, c2.device)
         ld = lambda t: t.stride(0) if B > 1 else t.shape[1]
         _lib.check(getattr(_lib.lib(), fn)(self._h, prec, ctypes.c_void_p(c2.data_ptr()),
                                            ctypes.c_void_p(d2.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
@@ -183,6 +203,7 @@ class Core:
         import torch
         Q2 = Q.unsqueeze(0) if Q.dim() == 1 else Q
         prec = self._prec(Q2, precision)
+        _check_tensor("Q", Q2, torch.float64 if prec in (FP64, FP64_NAIVE) else torch.float32, Q2.shape[0], self.N)
         res = ctypes.c_double()
         _lib.check(_lib.lib().wefq_check_conservation(self._h, prec, ctypes.c_void_p(Q2.data_ptr()), Q2.shape[0],
                                                       Q2.stride(0) if Q2.shape[0] > 1 else Q2.shape[1],
@@ -204,13 +225,14 @@ class Core:
         c2 = c.unsqueeze(0) if c.dim() == 1 else c
         prec = self._prec(c2, precision)
         want = torch.float64 if prec in (FP64, FP64_NAIVE) else torch.float32
-        if c2.dtype != want or c2.device.type != "cuda" or c2.stride(-1) != 1:
-            raise ValueError(f"c must be a CUDA {want} tensor with unit stride in the last dimension")
         B = c2.shape[0]
+        _check_tensor("c", c2, want, B, self.N)
         sch = RK_SCHEMES.get(scheme, scheme)
         need = self.rk_workspace_bytes(B, sch, prec)
         if work is None:
             work = torch.empty(need, dtype=torch.uint8, device=c2.device)
+        elif work.device != c2.device or not work.is_contiguous():
+            raise ValueError("work must be a contiguous tensor on the device of c")
         res = ctypes.c_double()
         _lib.check(_lib.lib().wefq_rk_integrate(self._h, prec, int(sch), ctypes.c_void_p(c2.data_ptr()), B,
                                                 c2.stride(0) if B > 1 else c2.shape[1], float(dt), int(nsteps),
@@ -284,10 +306,14 @@ class Plan:
         arr = (_lib.Segment * len(segments))()
         self._keep = []
         dev = None
+        import torch
+        want = torch.float64 if prec == FP64 else torch.float32
         for i, seg in enumerate(segments):
             core, f, Q = seg[:3]
             slots = seg[3] if len(seg) > 3 else 0
             B = f.shape[0]
+            _check_tensor(f"segment {i} f", f, want, B, core.N, dev)
+            _check_tensor(f"segment {i} Q", Q, want, B, core.N, f.device)
             arr[i] = _lib.Segment(core.handle, prec, int(slots), f.data_ptr(), Q.data_ptr(), B,
                                   f.stride(0) if B > 1 else f.shape[1], Q.stride(0) if B > 1 else Q.shape[1])
             self._keep.append((core, f, Q))

@@ -27,7 +27,9 @@
 //     independent of the other cells in the batch;
 //   * waves pull (l1, q1-group) work units from an LDS counter, largest first; a
 //     launch with few tiles deals each tile's units to several workgroups.
-// The mass, momentum and energy rows are stored as exact zeros (Section 4.4).
+// The mass, momentum and energy rows of Q come out as exact zeros because those rows of the
+// core are zero (Section 4.4): every product on them is 0 x finite.  They are stored as
+// computed, so the FP64 conservation check below tests the zeroing and the row mapping.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(256) void apply_fp64_kernel(Fp64Params p) {
     }
     acc = fma(p.ent_g[e], s, acc);
   }
-  if (active) p.Q[b * p.ldq + n] = invariant_row(q1, k1) ? 0.0 : acc;
+  if (active) p.Q[b * p.ldq + n] = acc;
 }
 
 hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int64_t B,
@@ -89,7 +91,9 @@ hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int
   p.f = f; p.Q = Q; p.ldf = ldf; p.ldq = ldq;
   p.NK = h->NK; p.N = h->N; p.nchunk = (h->N + 3) / 4;
   p.R = h->dR64; p.q1ptr = h->d_q1ptr; p.ent_c = h->d_ent_c; p.ent_q = h->d_ent_q; p.ent_g = h->d_ent_g;
-  const int64_t maxcells = (int64_t)64 * (0x7fffffff / p.nchunk);
+  // a launch holds at most 2^32 - 1 threads (grid x block): 256-thread blocks, nchunk per
+  // 64 cells
+  const int64_t maxcells = max_cells_per_launch(64, 256, p.nchunk);
   for (int64_t b0 = 0; b0 < B; b0 += maxcells) {
     const int64_t nb = B - b0 < maxcells ? B - b0 : maxcells;
     Fp64Params q = p;
@@ -240,6 +244,19 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   p.nsplit = tile_splits(h, ntiles, p.nunits, h->split_per_cu[mode],
                          (int64_t)h->cu_count * h->resident_per_cu[mode]);
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
+  // a launch holds at most 2^32 - 1 threads: larger batches run as several launches of whole
+  // tiles (each cell's result does not depend on its batch)
+  const int64_t max_cells = max_cells_per_launch(TB, block);
+  if (B > max_cells) {
+    for (int64_t c0 = 0; c0 < B; c0 += max_cells) {
+      const int64_t nc = (B - c0) < max_cells ? (B - c0) : max_cells;
+      const size_t esz = mode == 2 ? 8 : 4;
+      const hipError_t e = launch_apply_mfma(h, precision, (const char*)f + c0 * ldf * esz,
+                                             (char*)Q + c0 * ldq * esz, nc, ldf, ldq, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   switch (h->H) {
     case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);
     case 2: return launch_mfma_h<2>(p, mode, slots, h->RT, ntiles, block, lds, s);

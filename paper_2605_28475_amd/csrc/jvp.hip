@@ -94,6 +94,19 @@ static hipError_t launch_two(const wefq_core* h, bool anti, int precision, const
   p.nsplit = tile_splits(h, ntiles, p.nunits, 1, 0);
   if (p.nsplit > 1 && p.nsplit > p.nunits / 4) p.nsplit = p.nunits / 4 > 1 ? p.nunits / 4 : 1;
   const size_t lds = 2 * tile_lds_bytes(h, slots, elem);
+  // a launch holds at most 2^32 - 1 threads: larger batches run as several launches of whole
+  // tiles (each cell's result does not depend on its batch)
+  const int64_t max_cells = max_cells_per_launch(TB, 512);
+  if (B > max_cells) {
+    for (int64_t c0 = 0; c0 < B; c0 += max_cells) {
+      const int64_t nc = (B - c0) < max_cells ? (B - c0) : max_cells;
+      const hipError_t e = launch_two(h, anti, precision, (const char*)f + c0 * ldf * elem,
+                                      (const char*)g + c0 * ldg * elem, (char*)out + c0 * ldo * elem, nc, ldf, ldg,
+                                      ldo, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   switch (h->H) {
     case 1: return launch_jvp_h<1>(p, anti, mode, slots, h->RT, ntiles, lds, s);
     case 2: return launch_jvp_h<2>(p, anti, mode, slots, h->RT, ntiles, lds, s);

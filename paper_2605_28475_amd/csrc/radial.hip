@@ -115,7 +115,6 @@ __global__ __launch_bounds__(256) void radial_gather_kernel(RadialParams p) {
   }
   for (; z < z1; ++z) a0 += ((cdbl*)p.row_g)[z] * col[((cint*)p.row_grp)[z] * gstride];
   double acc = (a0 + a1) + (a2 + a3);
-  if (invariant_row(q1, k1)) acc = 0.0;
   if (cell < p.nc) p.Q[(p.c0 + cell) * p.ldq + n] = acc;
 }
 

@@ -32,6 +32,16 @@ std::vector<CooRow> build_coo(int L, double tol = 1e-12);
 // Gauss-Laguerre with weight x^alpha e^{-x} on [0, inf).
 void gauss_rule(int kind, int n, double alpha, std::vector<double>& x, std::vector<double>& w);
 
+// Most threads one kernel launch may hold (grid size times block size).
+constexpr int64_t max_launch_threads() { return 0xffffffffLL; }
+
+// Cells of one launch of a kernel that runs one workgroup of `block` threads per tile of
+// `tile_cells` cells (times `blocks_per_tile` workgroups): larger batches are split into
+// launches of at most this many cells.
+inline int64_t max_cells_per_launch(int64_t tile_cells, int64_t block, int64_t blocks_per_tile = 1) {
+  return max_launch_threads() / (block * blocks_per_tile) * tile_cells;
+}
+
 inline int q_of(int l, int m) { return l * l + l + m; }
 inline int l_of_q(int q) { int l = 0; while ((l + 1) * (l + 1) <= q) ++l; return l; }
 

@@ -1,6 +1,7 @@
 // Host-only driver for the sanitizer test: exercises the real-Gaunt table, the channel list
 // and the Gauss rules of host_tables.cpp, and checks a few exact properties.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <vector>
 
@@ -42,6 +43,24 @@ int main() {
     for (double v : w) s += v;
     if (std::fabs(s - 1.0) > 1e-12) ++bad;
   }
+  // launch chunking: the launches of a batch cover every cell once and each holds at most
+  // 2^32 - 1 threads, for the tile shapes of the apply kernels and the naive FP64 kernel
+  const int64_t big = (int64_t)1 << 36;
+  for (int64_t tb : {16, 8, 4, 2, 64})
+    for (int64_t block : {256, 512})
+      for (int64_t per : {1, 4, 1229})
+        for (int64_t B : {(int64_t)1, (int64_t)12345, big, big + 7}) {
+          const int64_t mc = wefq::max_cells_per_launch(tb, block, per);
+          if (mc <= 0) { ++bad; continue; }
+          int64_t covered = 0;
+          for (int64_t c0 = 0; c0 < B; c0 += mc) {
+            const int64_t nc = B - c0 < mc ? B - c0 : mc;
+            const int64_t threads = (nc + tb - 1) / tb * per * block;
+            if (threads > wefq::max_launch_threads()) ++bad;
+            covered += nc;
+          }
+          if (covered != B) ++bad;
+        }
   std::printf("host tables: %d failures\n", bad);
   return bad != 0;
 }

@@ -66,7 +66,7 @@ def test_angular_apply_matches_oracle(prec):
     f = torch.tensor(c, dtype=dt, device=dev())
     ref = oapply.apply_q(core_zeroed(K, L, 1.0, beta=BETA), coo(L), f.cpu().numpy().astype(np.float64), K)
     got = core.apply_Q(f, precision=prec).cpu().numpy().astype(np.float64)
-    tol = {"fp64": 1e-12, "fp64_naive": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}[prec]
+    tol = {"fp64": 1e-12, "fp64_naive": 1e-12, "fp32": 1e-5, "bf16x3": 3e-5}[prec]
     assert rel_err(got, ref) < tol
     assert np.all(got[:, invariant_indices(K, L)] == 0.0)
 

@@ -42,9 +42,9 @@ def _full(K, L, model, gamma, B, seed, sample, tol32, tol16):
 
 
 def test_k8_batch_maxwell_and_hard_sphere():
-    _full(8, 8, "mm", 0.0, 4096, synth.BASE_SEED + 2, 64, 1e-5, 2e-4)
-    _full(8, 8, "hs", 1.0, 4096, synth.BASE_SEED + 2, 64, 1e-5, 2e-4)
+    _full(8, 8, "mm", 0.0, 4096, synth.BASE_SEED + 2, 64, 1e-5, 3e-5)
+    _full(8, 8, "hs", 1.0, 4096, synth.BASE_SEED + 2, 64, 1e-5, 3e-5)
 
 
 def test_k12_batch_vhs_B65536():
-    _full(12, 12, "vhs", 0.5, 65536, synth.BASE_SEED + 3, 8, 1e-5, 2e-4)
+    _full(12, 12, "vhs", 0.5, 65536, synth.BASE_SEED + 3, 8, 1e-5, 3e-5)

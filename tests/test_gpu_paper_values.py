@@ -37,7 +37,10 @@ def test_table3_wang_chang_uhlenbeck_spectrum():
     ratio = ev / abs(ev[5])
     for first, last, r, bound in golden("table3_wcu.txt"):
         seg = ratio[int(first) - 1:int(last)]
-        assert np.abs(seg - float(r)).max() <= max(float(bound), 1e-15) * 10
+        dev_ = np.abs(seg - float(r)).max()
+        say(f"[table3] ratio {r}: max deviation {dev_:.1e} (printed bound {bound})")
+        # twice the printed bound, floored at 2e-14, the FP64 rounding of the operator's entries
+        assert dev_ <= max(2 * float(bound), 2e-14)
     assert ratio.min() >= -3.0
     assert abs(ev[5] - (-1.0 / 3.0)) < 1e-13
     core.close()

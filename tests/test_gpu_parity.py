@@ -14,7 +14,7 @@ from paper_2605_28475_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp64_naive": 1e-12, "fp32": 1e-5, "bf16x3": 2e-4}
+TOL = {"fp64": 1e-12, "fp64_naive": 1e-12, "fp32": 1e-5, "bf16x3": 3e-5}
 _cores = {}
 
 
@@ -241,7 +241,7 @@ def test_large_truncations_fp64_tiled_vs_naive(K, L):
     ref = run(core, c, "fp64_naive")
     assert rel_err(run(core, c, "fp64"), ref) < 1e-13
     assert rel_err(run(core, c, "fp32"), ref) < 1e-5
-    assert rel_err(run(core, c, "bf16x3"), ref) < 2e-4
+    assert rel_err(run(core, c, "bf16x3"), ref) < TOL["bf16x3"]
     core.close()
 
 
@@ -254,7 +254,7 @@ def test_rotation_equivariance_on_gpu(K, L, model, gamma):
     blocks = wigner_blocks(L, random_rotation(K + L))
     c = synth.perturbed_maxwellian(K, L, 6, seed=77)
     cr = rotate(c, K, L, blocks)
-    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5), ("bf16x3", 4e-4)):
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2 * TOL["fp32"]), ("bf16x3", 2 * TOL["bf16x3"])):
         q = run(core, c, prec)
         qr = run(core, cr, prec)
         assert rel_err(qr, rotate(q, K, L, blocks)) < tol, prec
@@ -307,3 +307,37 @@ def test_apply_q_argument_errors():
     assert torch.all(q == 3.0)
     assert L_.wefq_apply_Q(h, _lib.FP64, fp, qp, 0, N, N, None) == _lib.WEFQ_OK      # empty batch
     core.close()
+
+
+def test_binding_refuses_bad_tensors_before_launch():
+    """The binding checks every tensor the library would write through a bare pointer: dtype,
+    device, unit stride, rows and modes; nothing is launched (the output stays untouched)."""
+    K = L = 3
+    core = gpu_core("hs", K, L, 1.0)
+    d = dev()
+    N = core.N
+    f32 = torch.tensor(synth.perturbed_maxwellian(K, L, 6, seed=8), dtype=torch.float32, device=d)
+    f64 = f32.double()
+    good = torch.full((6, N), 5.0, dtype=torch.float32, device=d)
+    bad_outs = [torch.empty((6, N), dtype=torch.float64, device=d),          # wrong dtype
+                torch.empty((5, N), dtype=torch.float32, device=d),          # too few rows
+                torch.empty((6, N + 1), dtype=torch.float32, device=d),      # wrong mode count
+                torch.empty((6, 2 * N), dtype=torch.float32, device=d)[:, ::2],   # non-unit stride
+                torch.empty((6, N), dtype=torch.float32)]                    # host memory
+    for out in bad_outs:
+        with pytest.raises(ValueError):
+            core.apply_Q(f32, out=out)
+    with pytest.raises(ValueError):
+        core.apply_Q(f64, out=good, precision="fp64")                         # FP32 out for FP64
+    with pytest.raises(ValueError):
+        core.apply_Q(f32[:, :N - 1])                                          # f of the wrong size
+    with pytest.raises(ValueError):
+        core.apply_J(f32, f32, out=bad_outs[1])
+    with pytest.raises(ValueError):
+        core.check_conservation(torch.zeros((4, N + 3), dtype=torch.float32, device=d))
+    with pytest.raises(ValueError):
+        wefq.Plan([(core, f32, bad_outs[1])], precision="fp32")
+    with pytest.raises(ValueError):
+        wefq.Plan([(core, f64, torch.empty_like(f64))], precision="fp32")    # dtype of the plan
+    torch.cuda.synchronize()
+    assert torch.all(good == 5.0)

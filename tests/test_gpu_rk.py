@@ -14,7 +14,7 @@ from paper_2605_28475_amd import _lib, synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-12, "fp64_naive": 1e-12, "fp32": 1e-5, "bf16x3": 2e-4}
+TOL = {"fp64": 1e-12, "fp64_naive": 1e-12, "fp32": 1e-5, "bf16x3": 3e-5}
 _cores = {}
 
 
@@ -43,8 +43,14 @@ def test_rk_matches_oracle(scheme, prec):
     c = tensor(c0, prec)
     inv = core.rk_integrate(c, dt, n, scheme=scheme, precision=prec)
     got = c.cpu().numpy().astype(np.float64)
-    # the change over the run is what the operator contributes; compare it
-    assert rel_err(got - c0, ref - c0) < 10 * TOL[prec]
+    # The change over the run is what the operator contributes; compare it.  In FP32 storage
+    # every step's update of c rounds c itself (unit roundoff 2^-24 of |c| ~ 1, once per step),
+    # which the increment's relative error inherits; the bound is twice the precision's
+    # tolerance plus that rounding.
+    store = 0.0 if prec.startswith("fp64") else n * 2.0 ** -24 * np.abs(c0).max() / np.abs(ref - c0).max()
+    err = rel_err(got - c0, ref - c0)
+    say(f"[rk] {scheme} {prec}: increment error {err:.2e}, storage rounding {store:.2e}")
+    assert err < 2 * (TOL[prec] + store)
     assert inv == 0.0
     idx = invariant_indices(K, L)
     assert np.array_equal(got[:, idx], c0[:, idx])
