@@ -296,6 +296,24 @@ wefq_status wefq_rk_integrate(wefq_handle h, int32_t precision, int32_t scheme, 
                               double dt, int32_t nsteps, void* work, int64_t work_bytes, double* max_invariant,
                               void* stream);
 
+/* Bytes of the fixed device scratch that wefq_rk_integrate_noalloc uses (64 MiB per device). */
+#define WEFQ_RK_NOALLOC_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * time-stepping or serving loops, harnesses that forbid allocation): wefq_rk_integrate without
+ * a workspace argument.  The check state and the stage buffers live in a fixed device array of
+ * WEFQ_RK_NOALLOC_BYTES inside the library, one per device that the library runs on, held until
+ * the process ends; its device address is looked up on the first call on each device.  The call
+ * itself allocates nothing (no hipMalloc, hipFree or allocating library routine).  Arguments,
+ * results and errors as for wefq_rk_integrate, and WEFQ_EBUDGET when the workspace that
+ * wefq_rk_workspace reports for (precision, scheme, B) exceeds WEFQ_RK_NOALLOC_BYTES.  The check
+ * state is cleared by a kernel at the start of every call.  Every call on one device shares that
+ * device's scratch, which keeps the last call's contents: calls that overlap on one device
+ * (several streams or threads) race, so the caller serializes them.  Under graph capture pass
+ * max_invariant = NULL (the readback synchronizes the stream). */
+wefq_status wefq_rk_integrate_noalloc(wefq_handle h, int32_t precision, int32_t scheme, void* c, int64_t B,
+                                      int64_t ld, double dt, int32_t nsteps, double* max_invariant, void* stream);
+
 /* ---- measurement helper ---- */
 
 /* What the rate probe measures. */

@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "EUNSUPPORTED",
 
 
 MAX_BETA = 33          # WEFQ_MAX_BETA
+RK_NOALLOC_BYTES = 64 << 20   # WEFQ_RK_NOALLOC_BYTES
 
 
 class CoreDesc(ctypes.Structure):
@@ -94,6 +95,9 @@ _SIGNATURES = [
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                          ctypes.c_void_p]),
+    ("wefq_rk_integrate_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     ("wefq_peak_probe", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.c_void_p]),
 ]

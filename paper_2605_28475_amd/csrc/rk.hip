@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "../../include/wefq.h"
@@ -141,6 +142,31 @@ static hipError_t rk_run(wefq_core* h, int precision, const Tableau& tb, T* c, i
   return e;
 }
 
+// Fixed device scratch of wefq_rk_integrate_noalloc: the check state and the stage buffers,
+// laid out as the caller-owned workspace of wefq_rk_integrate.  Every device the library runs
+// on holds its own copy until the process ends.  Host code never passes this name to a
+// kernel (on the host it is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) char rk_scratch[WEFQ_RK_NOALLOC_BYTES];
+
+static std::mutex rk_scratch_mu;
+static char* rk_scratch_ptr[64];
+
+// Device address of rk_scratch on the current device (the caller has selected it).
+static hipError_t rk_scratch_address(int device, char** out) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(rk_scratch_mu);
+  if (!rk_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(rk_scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    rk_scratch_ptr[device] = static_cast<char*>(p);
+  }
+  *out = rk_scratch_ptr[device];
+  return hipSuccess;
+}
+
 }  // namespace wefq
 
 using namespace wefq;
@@ -170,9 +196,13 @@ wefq_status wefq_rk_workspace(wefq_handle h, int32_t precision, int32_t scheme, 
   return WEFQ_OK;
 }
 
-wefq_status wefq_rk_integrate(wefq_handle h, int32_t precision, int32_t scheme, void* c, int64_t B, int64_t ld,
-                              double dt, int32_t nsteps, void* work, int64_t work_bytes, double* max_invariant,
-                              void* stream) {
+}  // extern "C"
+
+// Shared by wefq_rk_integrate (caller workspace) and wefq_rk_integrate_noalloc (the fixed
+// device scratch, work == nullptr): argument checks, the stepping, the optional readback.
+static wefq_status rk_integrate_impl(wefq_handle h, int32_t precision, int32_t scheme, void* c, int64_t B, int64_t ld,
+                                     double dt, int32_t nsteps, void* work, int64_t work_bytes, double* max_invariant,
+                                     void* stream, bool fixed_scratch) {
   if (!h) return rk_fail(WEFQ_EINVAL, "null handle");
   const Tableau* tb = tableau(scheme);
   if (!tb) return rk_fail(WEFQ_EINVAL, "unknown Runge-Kutta scheme");
@@ -181,17 +211,28 @@ wefq_status wefq_rk_integrate(wefq_handle h, int32_t precision, int32_t scheme, 
   if (!(dt == dt) || dt > 1e300 || dt < -1e300) return rk_fail(WEFQ_EINVAL, "time step must be finite");
   if (max_invariant) *max_invariant = 0.0;
   if (B == 0 || nsteps == 0) return WEFQ_OK;
-  if (!c || !work) return rk_fail(WEFQ_EINVAL, "null coefficient or workspace pointer");
+  if (!c || (!work && !fixed_scratch)) return rk_fail(WEFQ_EINVAL, "null coefficient or workspace pointer");
   if (ld < h->N) return rk_fail(WEFQ_EINVAL, "leading dimension smaller than N");
   const int64_t elem = (precision == WEFQ_FP64 || precision == WEFQ_FP64_NAIVE) ? 8 : 4;
+  const int64_t need = 256 + (int64_t)(tb->stages + 1) * B * h->N * elem;
+  if (fixed_scratch && need > (int64_t)WEFQ_RK_NOALLOC_BYTES)
+    return rk_fail(WEFQ_EBUDGET, "batch needs " + std::to_string(need) + " bytes of stage buffers, more than the " +
+                                     std::to_string((long long)WEFQ_RK_NOALLOC_BYTES) +
+                                     "-byte fixed scratch (WEFQ_RK_NOALLOC_BYTES); use wefq_rk_integrate");
+  if (hipSetDevice(h->device) != hipSuccess) return rk_fail(WEFQ_EHIP, "hipSetDevice failed");
+  if (fixed_scratch) {
+    char* p = nullptr;
+    const hipError_t e = rk_scratch_address(h->device, &p);
+    if (e != hipSuccess) return rk_fail(WEFQ_EHIP, std::string("fixed scratch address: ") + hipGetErrorString(e));
+    work = p;
+    work_bytes = (int64_t)WEFQ_RK_NOALLOC_BYTES;
+  }
   if (((uintptr_t)c & (uintptr_t)(elem - 1)) || ((uintptr_t)work & 255))
     return rk_fail(WEFQ_EINVAL, "c must be aligned to the element size and the workspace to 256 bytes");
-  const int64_t need = 256 + (int64_t)(tb->stages + 1) * B * h->N * elem;
   if (work_bytes < need) return rk_fail(WEFQ_EINVAL, "workspace smaller than wefq_rk_workspace reports");
   const char* cb = (const char*)c;
   const char* wb = (const char*)work;
   if (cb < wb + need && wb < cb + (size_t)B * ld * elem) return rk_fail(WEFQ_EINVAL, "c and the workspace overlap");
-  if (hipSetDevice(h->device) != hipSuccess) return rk_fail(WEFQ_EHIP, "hipSetDevice failed");
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = elem == 8 ? rk_run<double>(h, precision, *tb, (double*)c, B, ld, dt, nsteps, (char*)work, s)
                            : rk_run<float>(h, precision, *tb, (float*)c, B, ld, dt, nsteps, (char*)work, s);
@@ -207,6 +248,20 @@ wefq_status wefq_rk_integrate(wefq_handle h, int32_t precision, int32_t scheme, 
     *max_invariant = v;
   }
   return WEFQ_OK;
+}
+
+extern "C" {
+
+wefq_status wefq_rk_integrate(wefq_handle h, int32_t precision, int32_t scheme, void* c, int64_t B, int64_t ld,
+                              double dt, int32_t nsteps, void* work, int64_t work_bytes, double* max_invariant,
+                              void* stream) {
+  return rk_integrate_impl(h, precision, scheme, c, B, ld, dt, nsteps, work, work_bytes, max_invariant, stream,
+                           false);
+}
+
+wefq_status wefq_rk_integrate_noalloc(wefq_handle h, int32_t precision, int32_t scheme, void* c, int64_t B,
+                                      int64_t ld, double dt, int32_t nsteps, double* max_invariant, void* stream) {
+  return rk_integrate_impl(h, precision, scheme, c, B, ld, dt, nsteps, nullptr, 0, max_invariant, stream, true);
 }
 
 }  // extern "C"
