@@ -394,13 +394,14 @@ def bench_orderings(args, torch, wefq, synth):
     """The orderings of the factorized sum (Section 4.5) on one GPU, FP64, hard spheres,
     K = 4 and L = 2..13, 16,384 cells: naive (every table row contracts its NK^3 block; on
     2,048 cells), radial-first (the dense intermediate Psi through HBM, then one pass over the
-    table) and angular-first (the tiled MFMA kernel).  The dense Cartesian contraction is not
-    run; its count, 2 N^3 FLOPs per cell, is given for reference.  One more point compares
-    radial-first with angular-first at K = L = 12 (VHS 0.5, 1,024 cells)."""
+    table), angular-first (the tiled MFMA kernel) and the dense Cartesian contraction of
+    Section 4.5.1 (the full N^3 tensor C assembled in HBM, 2 N^3 FLOPs per cell on the FP64
+    matrix cores; on 2,048 cells).  One more point compares radial-first with angular-first at
+    K = L = 12 (VHS 0.5, 1,024 cells)."""
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    K, B, nb_naive = 4, 16384, 2048
+    K, B, nb_naive, nb_dense = 4, 16384, 2048, 2048
     rows = []
     for L in (2, 4, 6, 8, 10, 12, 13):
         log(f"[orderings] K={K} L={L}")
@@ -420,23 +421,37 @@ def bench_orderings(args, torch, wefq, synth):
         fn, qn = f[:nb_naive], torch.empty_like(f[:nb_naive])
         core.apply_Q(fn, out=qn, precision="fp64_naive")
         ms_n, _ = time_steps(lambda: core.apply_Q(fn, out=qn, precision="fp64_naive"), 2, stream, torch)
+        log(f"[orderings] dense, C {core.dense_bytes() / 2**30:.2f} GiB")
+        Cd = torch.empty(core.dense_bytes(), dtype=torch.uint8, device=dev)
+        ms_asm, _ = time_steps(lambda: core.dense_assemble(Cd), 1, stream, torch)
+        fd, qd = f[:nb_dense], torch.empty_like(f[:nb_dense])
+        core.apply_Q_dense(Cd, fd, out=qd)
+        ms_d, _ = time_steps(lambda: core.apply_Q_dense(Cd, fd, out=qd), 3, stream, torch)
         scale = q.abs().max().item()
         err_r = (qr - q).abs().max().item() / scale
         err_n = (qn - q[:nb_naive]).abs().max().item() / scale
-        t_a, t_r, t_n = (float(np.mean(m)) * 1e-3 for m in (ms_a, ms_r, ms_n))
+        err_d = (qd - q[:nb_dense]).abs().max().item() / scale
+        t_a, t_r, t_n, t_d = (float(np.mean(m)) * 1e-3 for m in (ms_a, ms_r, ms_n, ms_d))
+        dense_tflops = 2.0 * N ** 3 * nb_dense / t_d / 1e12
         groups = info["radial_groups"]
         psi_bytes = 2.0 * groups * NK * 8 + 2.0 * N * 8          # Psi and the transposed f, written and read
         rows.append({"L": L, "N": N, "N_G": info["N_G"], "N_S": info["N_S"], "radial_groups": groups,
                      "angular_first_cells_per_s": B / t_a, "radial_first_cells_per_s": B / t_r,
                      "naive_cells_per_s": nb_naive / t_n,
+                     "dense_cells_per_s": nb_dense / t_d, "dense_tflops": dense_tflops,
+                     "dense_frac_fp64_peak": dense_tflops / PEAK["fp64"], "dense_assembly_ms": float(ms_asm[0]),
+                     "dense_tensor_gib": core.dense_bytes() / 2 ** 30,
+                     "angular_vs_dense": (B / t_a) / (nb_dense / t_d),
                      "angular_vs_naive": (B / t_a) / (nb_naive / t_n), "angular_vs_radial": t_r / t_a,
                      "radial_vs_naive": (B / t_r) / (nb_naive / t_n),
                      "flop_per_cell": {"angular_first": info["flop_alg_per_cell"],
                                        "radial_first": 2.0 * groups * (NK ** 3 + NK ** 2) + 2.0 * NK * info["N_G"],
                                        "naive": 2.0 * NK ** 3 * info["N_G"], "dense": 2.0 * N ** 3},
                      "radial_first_hbm_gb_s": psi_bytes * B / t_r / 1e9, "radial_chunk_cells": chunk,
-                     "rel_err_vs_angular": {"radial_first": err_r, "naive": err_n}})
-        del f, q, qr, work, fn, qn
+                     "rel_err_vs_angular": {"radial_first": err_r, "naive": err_n, "dense": err_d}})
+        log(f"[orderings] L={L}: angular {B / t_a:.3e}, radial {B / t_r:.3e}, naive {nb_naive / t_n:.3e}, "
+            f"dense {nb_dense / t_d:.3e} cells/s ({dense_tflops:.1f} TFLOP/s)")
+        del f, q, qr, work, fn, qn, Cd, fd, qd
         core.close()
     # the headline truncation: which ordering an apply should use at K = L = 12
     log("[orderings] K=L=12 (1,024 cells)")

@@ -175,6 +175,27 @@ wefq_status wefq_radial_workspace(wefq_handle h, int64_t chunk, int64_t* bytes);
 wefq_status wefq_apply_Q_radial(wefq_handle h, const double* f, double* Q, int64_t B, int64_t ld_f,
                                 int64_t ld_q, void* work, int64_t work_bytes, void* stream);
 
+/* ---- the dense Cartesian contraction (Section 4.5.1), the paper's comparison baseline ---- */
+
+/* Bytes of the dense weak-form tensor C of a core for wefq_dense_assemble:
+ * 16 ceil(N/16) * N * 4 ceil(N/4) doubles (7.6 GB at Kmax = 4, Lmax = 13).  EINVAL without the
+ * WEFQ_FP64 tables; EUNSUPPORTED for N > 1280 (the contraction stages a 16-cell tile of f in LDS). */
+wefq_status wefq_dense_bytes(wefq_handle h, int64_t* bytes);
+
+/* Assemble the full tensor C_{a1 a2 a3} = g_{q1 q2 q3} R^{(c)}_{k1 k2 k3} (the factorization of
+ * Section 4.1 undone; zero where no Gaunt row exists) into C, caller-owned device memory of at
+ * least wefq_dense_bytes bytes, 256-byte aligned, in the layout of the contraction's matrix-core
+ * operand (documented in dense.hip).  Asynchronous on stream; allocates nothing. */
+wefq_status wefq_dense_assemble(wefq_handle h, void* C, int64_t C_bytes, void* stream);
+
+/* Q = Q(f, f) by the dense Cartesian contraction Q_a1 = sum_{a2, a3} C_{a1 a2 a3} f_a2 f_a3 in
+ * FP64 (Section 4.5.1): a reference ordering for comparison with wefq_apply_Q, 2 N^3 flops per
+ * cell.  C as assembled by wefq_dense_assemble; f, Q as for wefq_apply_Q in FP64 (double,
+ * [B][ld], ld >= N); Q must not overlap f or C.  Its invariant rows are exactly 0 for finite f
+ * (those rows of C are zero).  Asynchronous on stream; allocates nothing.  B == 0 is a no-op. */
+wefq_status wefq_apply_Q_dense(wefq_handle h, const void* C, int64_t C_bytes, const double* f, double* Q, int64_t B,
+                               int64_t ld_f, int64_t ld_q, void* stream);
+
 /* Jacobian-vector product out = J(c) d = Q(c, d) + Q(d, c), the derivative of Q(f, f)
  * at f = c in the direction d, where Q(f, g) = sum C_{a1 a2 a3} f_a2 g_a3 is the
  * bilinear form of Section 2.3 (so J(c) c = 2 Q(c, c) and J(e_000) is the linearized

@@ -168,6 +168,44 @@ class Core:
                                                   _stream_ptr(stream, f.device)))
         return out
 
+    def dense_bytes(self):
+        """Bytes of the dense weak-form tensor C (wefq_dense_bytes; needs the FP64 tables)."""
+        n = ctypes.c_int64()
+        _lib.check(_lib.lib().wefq_dense_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def dense_assemble(self, C=None, stream=None):
+        """Assemble the dense tensor C = g R (wefq_dense_assemble) into a uint8 device tensor of
+        dense_bytes() bytes (allocated here when None) and return it."""
+        import torch
+        nb = self.dense_bytes()
+        if C is None:
+            C = torch.empty(nb, dtype=torch.uint8, device=torch.device("cuda", self.device))
+        elif C.device.type != "cuda" or not C.is_contiguous() or C.numel() * C.element_size() < nb:
+            raise ValueError(f"C must be a contiguous device tensor of at least {nb} bytes")
+        _lib.check(_lib.lib().wefq_dense_assemble(self._h, ctypes.c_void_p(C.data_ptr()), C.numel() * C.element_size(),
+                                                  _stream_ptr(stream, C.device)))
+        return C
+
+    def apply_Q_dense(self, C, f, out=None, stream=None):
+        """Q(f, f) in FP64 by the dense Cartesian contraction with an assembled C (wefq_apply_Q_dense)."""
+        import torch
+        if f.dim() != 2:
+            raise ValueError("f must be a [B, N] tensor")
+        B = f.shape[0]
+        _check_tensor("f", f, torch.float64, B, self.N)
+        if C.device != f.device or not C.is_contiguous():
+            raise ValueError("C must be a contiguous tensor on the device of f")
+        if out is None:
+            out = torch.empty((B, self.N), dtype=torch.float64, device=f.device)
+        else:
+            _check_tensor("out", out, torch.float64, B, self.N, f.device)
+        _lib.check(_lib.lib().wefq_apply_Q_dense(self._h, ctypes.c_void_p(C.data_ptr()), C.numel() * C.element_size(),
+                                                 ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
+                                                 f.stride(0) if B > 1 else self.N,
+                                                 out.stride(0) if B > 1 else self.N, _stream_ptr(stream, f.device)))
+        return out
+
     def apply_J(self, c, d, out=None, precision=None, stream=None):
         """Jacobian-vector product J(c) d = Q(c, d) + Q(d, c) for [B, N] device tensors."""
         return self._two_input("wefq_apply_J", c, d, out, precision, stream)

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libwefq.so")
 
-SOURCES = ["host_tables.cpp", "capi.cpp", "core_build.hip", "apply.hip", "plan.hip", "rk.hip", "jvp.hip", "radial.hip", "peak.hip"]
+SOURCES = ["host_tables.cpp", "capi.cpp", "core_build.hip", "apply.hip", "plan.hip", "rk.hip", "jvp.hip", "radial.hip", "dense.hip", "peak.hip"]
 ARCH = os.environ.get("WEFQ_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
