@@ -162,6 +162,9 @@ def main():
                          "jvp: Jacobian-vector products J(c) d on the headline batch; "
                          "build: radial core build times, isotropic and with angular factors, and reload; "
                          "orderings: naive, radial-first and angular-first FP64 at K = 4, L = 2..13")
+    ap.add_argument("--tick-ms", type=float, default=16.0, help="serve: work per scheduling tick, in ms")
+    ap.add_argument("--serve-depth", type=int, default=2, help="serve: launches in flight")
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=None, help="serve: arrival rates (req/s)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of f (known byte count) for counter scaling")
     args = ap.parse_args()
@@ -573,7 +576,8 @@ def bench_rk(args, torch, wefq, synth):
 
 def bench_uneven(args, torch, wefq, synth):
     """20000 cells, K = L drawn from {4, 8, 12, 16}, hard spheres or VHS 0.5, FP32, one
-    persistent graph-captured launch with autotuned tiles, against separate launches."""
+    persistent graph-captured launch with tile shapes chosen by the autotuner on whole plans,
+    against the default shapes and against separate launches."""
     from paper_2605_28475_amd import autotune
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
@@ -582,7 +586,7 @@ def bench_uneven(args, torch, wefq, synth):
     total = cfg["cells"]
     size = rng.choice(np.array(cfg["sizes"]), size=total)
     model = rng.choice(np.array(["hs", "vhs"]), size=total)
-    segs, lds_max, flop = [], [], 0.0
+    segs, flop = [], 0.0
     for K in cfg["sizes"]:
         for m in ("hs", "vhs"):
             B = int(np.sum((size == K) & (model == m)))
@@ -590,34 +594,23 @@ def bench_uneven(args, torch, wefq, synth):
                 continue
             log(f"[uneven] core {m} K=L={K}, {B} cells")
             core = wefq.Core(m, K, K, gamma=1.0 if m == "hs" else 0.5, device=0, precisions=("fp32",))
-            s_lds = core.tune_get("fp32")[0]  # the library default, read before tuning
-            s, blk, _ = autotune.tune(core, "fp32", cells=min(B, 4096), reps=2)
             f = torch.tensor(synth.perturbed_maxwellian(K, K, B, seed=cfg["seed"] + 10 * K + (m == "hs")),
                              dtype=torch.float32, device=dev)
-            segs.append((core, f, torch.empty_like(f), s))
-            lds_max.append(s_lds)
+            segs.append((core, f, torch.empty_like(f)))
             flop += core.info["flop_alg_per_cell"] * B
-    # plan-level choice: per-core autotuned shapes (tuned on each segment alone), or the
-    # library's default shapes (largest tiles that fit LDS: fewer coefficient-tile reloads
-    # per cell, which pays once the whole mix fills the chip), each at 256 or 512 threads
-    default = [(c, f, q, s) for (c, f, q, _), s in zip(segs, lds_max)]
-    best = None
-    for name, cand in (("autotuned", segs), ("default", default)):
-        for blk in (256, 512):
-            plan = wefq.Plan(cand, precision="fp32", block=blk)
-            plan.launch()
-            ms, _ = time_steps(lambda: plan.launch(), 3, stream, torch)
-            log(f"[uneven] plan {name} block {blk}: {np.mean(ms):.2f} ms")
-            if best is None or np.mean(ms) < best[1]:
-                best = (plan, float(np.mean(ms)), blk, name, cand)
-    plan, _, blk, shape_name, segs_used = best
+    log("[uneven] autotuning whole plans")
+    slots, blk, tried = autotune.tune_plan(segs, "fp32")
+    default_ms = tried["block=512 slots=" + ",".join("0" for _ in segs)]
+    segs_used = [(c, f, q, s if s else c.tune_get("fp32")[0]) for (c, f, q), s in zip(segs, slots)]
+    plan = wefq.Plan(segs_used, precision="fp32", block=blk)
+    shape_name = "autotuned on whole plans"
     for _ in range(args.warmup):
         plan.launch()
     ms, wall = time_steps(lambda: plan.launch(), args.steps, stream, torch)
     ms_direct, _ = time_steps(lambda: plan.launch(graph=False), args.steps, stream, torch)
 
     def separate():
-        for core, f, q, _ in segs:
+        for core, f, q, _ in segs_used:
             core.apply_Q(f, out=q)
     ms_sep, _ = time_steps(separate, args.steps, stream, torch)
     t = float(np.mean(ms)) * 1e-3
@@ -633,7 +626,8 @@ def bench_uneven(args, torch, wefq, synth):
            "roofline": {"bound": "mfma", "achieved": flop / t / 1e12, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                         "frac": flop / t / 1e12 / PEAK["fp32"], "traffic": None},
            "graph_ms": float(np.mean(ms)), "direct_ms": float(np.mean(ms_direct)),
-           "separate_launches_ms": float(np.mean(ms_sep))}
+           "separate_launches_ms": float(np.mean(ms_sep)), "default_shapes_ms": default_ms,
+           "autotune_candidates_ms": tried}
     print(json.dumps(out), flush=True)
 
 

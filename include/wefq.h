@@ -287,6 +287,32 @@ wefq_status wefq_plan_info(wefq_plan p, int64_t* work_items, int64_t* lds_bytes,
 /* Release the plan (its graph and device work list); the caller synchronizes first. */
 wefq_status wefq_plan_destroy(wefq_plan p);
 
+/* ---- runners: one persistent launch per call over any mix of segments (serving) ---- */
+
+typedef struct wefq_runner_s* wefq_runner;
+
+/* A runner launches the persistent kernel of wefq_plan_create once per wefq_runner_launch over
+ * the segments of that call, with no graph and no allocation per call: the scheduling tick of
+ * a continuous-batching server, where the set of (core, cells) changes from one launch to the
+ * next (the spatial batching of Section 4.5 over requests of several truncations and models).
+ * It owns a ring of 4 slots, each a device work list of max_segments descriptors and max_items
+ * work items with a pinned host staging copy.  precision: FP32, BF16X3 or FP64 for every
+ * segment; block: 256 or 512 threads.  EINVAL for bad arguments, ENOMEM when the slots cannot
+ * be allocated. */
+wefq_status wefq_runner_create(int32_t device, int32_t precision, int32_t max_segments, int32_t max_items,
+                               int32_t block, wefq_runner* out);
+
+/* One persistent launch over nseg segments (layout, rules and per-cell results as for
+ * wefq_plan_create: bitwise those of wefq_apply_Q).  Builds the work list on the host, copies it
+ * into the next ring slot and enqueues the counter reset and the kernel on stream; returns without
+ * waiting, except when the slot's previous launch is still running (then it waits for that one).
+ * Segment buffers must stay valid until the launch completes.  EBUDGET when the batch needs more
+ * work items than max_items; nseg = 0 or a batch without cells launches nothing. */
+wefq_status wefq_runner_launch(wefq_runner r, int32_t nseg, const wefq_segment* segs, void* stream);
+
+/* Wait for the runner's launches and release it.  EINVAL for NULL. */
+wefq_status wefq_runner_destroy(wefq_runner r);
+
 /* ---- time integration: batched explicit Runge-Kutta stepping of dc/dt = Q(c) ---- */
 
 /* With the identity mass matrix the Galerkin weak form is an ODE system per cell

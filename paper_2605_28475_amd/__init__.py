@@ -379,3 +379,49 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class Runner:
+    """One persistent launch per call over any mix of segments (wefq_runner_*): the scheduling
+    tick of the continuous-batching server.  Segments are (core, f, Q) with f, Q CUDA tensors of
+    shape [B_i, N_i]; they must stay alive until the launch has completed (the caller records
+    an event after launch())."""
+
+    def __init__(self, device=0, precision="fp32", max_segments=4096, max_items=1 << 20, block=512):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.prec = prec
+        self.device = device
+        self.max_segments = int(max_segments)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().wefq_runner_create(int(device), prec, self.max_segments, int(max_items), int(block),
+                                                 ctypes.byref(h)))
+        self._h = h
+        self._arr = (_lib.Segment * self.max_segments)()
+
+    def launch(self, segments, stream=None):
+        import torch
+        want = torch.float64 if self.prec == FP64 else torch.float32
+        n = len(segments)
+        if n > self.max_segments:
+            raise ValueError(f"at most {self.max_segments} segments per launch")
+        dev = None
+        for i, (core, f, Q) in enumerate(segments):
+            B = f.shape[0]
+            _check_tensor(f"segment {i} f", f, want, B, core.N, dev)
+            _check_tensor(f"segment {i} Q", Q, want, B, core.N, f.device)
+            dev = f.device
+            self._arr[i] = _lib.Segment(core.handle, self.prec, 0, f.data_ptr(), Q.data_ptr(), B,
+                                        f.stride(0) if B > 1 else core.N, Q.stride(0) if B > 1 else core.N)
+        _lib.check(_lib.lib().wefq_runner_launch(self._h, n, ctypes.cast(self._arr, ctypes.c_void_p),
+                                                 _stream_ptr(stream, dev if dev is not None else self.device)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.check(_lib.lib().wefq_runner_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -94,6 +94,10 @@ _SIGNATURES = [
     ("wefq_plan_info", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int64)]),
     ("wefq_plan_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("wefq_runner_create", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    ("wefq_runner_launch", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    ("wefq_runner_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("wefq_rk_workspace", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_int64)]),
     ("wefq_rk_integrate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,

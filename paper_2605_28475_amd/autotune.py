@@ -72,3 +72,61 @@ def tune(core, precision="fp32", cells=4096, reps=3, use_cache=True):
         db[key] = {"slots": s, "block": b, "ms": timings}
         _save(db)
     return s, b, timings
+
+
+def _time_plan(plan, stream, reps):
+    import torch
+    plan.launch(stream=stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, e in evs:
+        a.record(stream)
+        plan.launch(stream=stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(e) for a, e in evs]))
+
+
+def tune_plan(segments, precision="fp32", blocks=(512, 256), reps=3):
+    """Tile shapes for a whole uneven batch, chosen by timing whole plans (graph replays), not
+    segments alone: a shape that wins for a core on its own can lose inside the mix, where
+    the persistent kernel's LDS size and residency are set by the largest tile and the work
+    items of every core compete for the same workgroups.
+
+    segments: list of (core, f, Q).  Coordinate descent: start from every core's default shape
+    at the first block size; then, core by core in decreasing share of the plan's FLOPs, try
+    every slots value with the others held, keeping the fastest; then every block size.
+    Returns (slots per segment, block, {candidate: ms}); per-cell results do not depend on it."""
+    import torch
+    from . import Plan, WefqError
+    stream = torch.cuda.current_stream(segments[0][1].device)
+    slots = [0] * len(segments)
+    block = blocks[0]
+    timings = {}
+
+    def measure(sl, blk):
+        key = f"block={blk} slots=" + ",".join(str(x) for x in sl)
+        if key not in timings:
+            try:
+                plan = Plan([(c, f, q, s) for (c, f, q), s in zip(segments, sl)], precision=precision, block=blk)
+            except WefqError:
+                timings[key] = float("inf")        # a tile that does not fit in LDS
+                return timings[key]
+            timings[key] = _time_plan(plan, stream, reps)
+            plan.close()
+        return timings[key]
+
+    best = measure(slots, block)
+    order = sorted(range(len(segments)),
+                   key=lambda i: -segments[i][0].info["flop_alg_per_cell"] * segments[i][1].shape[0])
+    for i in order:
+        for s in (1, 2, 4):
+            trial = list(slots)
+            trial[i] = s
+            t = measure(trial, block)
+            if t < best:
+                best, slots = t, trial
+    for blk in blocks[1:]:
+        t = measure(slots, blk)
+        if t < best:
+            best, block = t, blk
+    return slots, block, timings

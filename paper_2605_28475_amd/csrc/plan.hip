@@ -122,13 +122,28 @@ static hipError_t plan_enqueue(const wefq_plan_s* p, hipStream_t s) {
   return hipGetLastError();
 }
 
-extern "C" {
+// Kernel of a plan precision (mode 0 FP32, 1 BF16X3, 2 FP64).
+static const void* persistent_kernel(int mode) {
+  return mode == 0 ? (const void*)apply_persistent_kernel<0>
+         : mode == 1 ? (const void*)apply_persistent_kernel<1> : (const void*)apply_persistent_kernel<2>;
+}
 
-wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t block, void* stream,
-                             wefq_plan* out) {
-  if (!out || !segs || nseg <= 0) return plan_fail(WEFQ_EINVAL, "plan needs at least one segment and an output");
-  *out = nullptr;
-  if (block != 256 && block != 512) return plan_fail(WEFQ_EINVAL, "block must be 256 or 512");
+// A batch of segments made into a work list: the per-segment parameters and the item codes,
+// largest first.
+struct WorkList {
+  int mode = 0;
+  int device = -1;
+  size_t lds = 0;
+  std::vector<SegDesc> descs;
+  std::vector<int64_t> codes;
+};
+
+// Validate the segments and build their descriptors (any mix of cores of one precision on one
+// device).  Items are made by make_items once the residency is known.
+static wefq_status describe_segments(int32_t nseg, const wefq_segment* segs, WorkList& w,
+                                     std::vector<int64_t>& seg_tiles, std::vector<double>& seg_cost,
+                                     std::vector<int>& seg_units) {
+  if (!segs || nseg <= 0) return plan_fail(WEFQ_EINVAL, "at least one segment is needed");
   const int prec = segs[0].precision;
   if (prec != WEFQ_FP32 && prec != WEFQ_BF16X3 && prec != WEFQ_FP64)
     return plan_fail(WEFQ_EINVAL, "plan precision must be FP32, BF16X3 or FP64");
@@ -136,11 +151,13 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
   const size_t elem = mode == 2 ? 8 : 4;
   const int device = segs[0].core ? segs[0].core->device : -1;
   if (nseg >= (1 << 15)) return plan_fail(WEFQ_EINVAL, "too many segments");
-  std::vector<SegDesc> descs(nseg);
-  std::vector<int64_t> seg_tiles(nseg);
-  std::vector<double> seg_cost(nseg);
-  std::vector<int> seg_units(nseg);
-  size_t lds = 0;
+  w.mode = mode;
+  w.device = device;
+  w.lds = 0;
+  w.descs.assign(nseg, SegDesc());
+  seg_tiles.assign(nseg, 0);
+  seg_cost.assign(nseg, 0.0);
+  seg_units.assign(nseg, 0);
   for (int i = 0; i < nseg; ++i) {
     const wefq_segment& g = segs[i];
     wefq_core* h = g.core;
@@ -157,8 +174,8 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     const int TB = 16 / slots;
     const size_t need = tile_lds_bytes(h, slots, elem);
     if (need > (size_t)h->lds_limit) return plan_fail(WEFQ_EUNSUPPORTED, "segment tile does not fit in LDS");
-    lds = std::max(lds, need);
-    SegDesc& d = descs[i];
+    w.lds = std::max(w.lds, need);
+    SegDesc& d = w.descs[i];
     std::memset(&d, 0, sizeof(d));
     MfmaParams& p = d.p;
     p.f = g.f; p.g = nullptr; p.Q = g.Q; p.B = g.B; p.ldf = g.ld_f; p.ldg = 0; p.ldq = g.ld_q;
@@ -175,20 +192,18 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
     seg_cost[i] = h->tile_cost * (double)TB / 16.0;
     seg_units[i] = h->nunits;
   }
-  if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
-  const void* k = mode == 0 ? (const void*)apply_persistent_kernel<0>
-                  : mode == 1 ? (const void*)apply_persistent_kernel<1> : (const void*)apply_persistent_kernel<2>;
-  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
-  int per_cu = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 1;
-  // Work items: (segment, cell tile, split), largest first.  A tile whose cost exceeds a
-  // third of a workgroup's fair share is split over several workgroups (its work units
-  // dealt round-robin, as in a small-batch launch), so that the last items are short.
+  return WEFQ_OK;
+}
+
+// Work items: (segment, cell tile, split), largest first.  A tile whose cost exceeds a third of a
+// workgroup's fair share is split over several workgroups (its work units dealt round-robin, as
+// in a small-batch launch), so that the last items are short.
+static wefq_status make_items(WorkList& w, const std::vector<int64_t>& seg_tiles, const std::vector<double>& seg_cost,
+                              const std::vector<int>& seg_units, int resident) {
+  const int nseg = (int)w.descs.size();
   double total = 0.0;
   for (int i = 0; i < nseg; ++i) total += seg_cost[i] * (double)seg_tiles[i];
-  const double target = total / (3.0 * (double)per_cu * (double)cus);
+  const double target = total / (3.0 * (double)resident);
   std::vector<std::pair<double, int64_t>> items;
   for (int i = 0; i < nseg; ++i) {
     int ns = 1;
@@ -196,7 +211,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
       const int cap = std::max(1, std::min(255, seg_units[i] / 4));
       ns = (int)std::min<double>(cap, std::ceil(seg_cost[i] / target));
     }
-    descs[i].p.nsplit = ns;
+    w.descs[i].p.nsplit = ns;
     for (int64_t t = 0; t < seg_tiles[i]; ++t)
       for (int sp = 0; sp < ns; ++sp)
         items.push_back({seg_cost[i] / ns, ((int64_t)i << 48) | ((int64_t)sp << 40) | t});
@@ -204,11 +219,50 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
   if (items.size() > 0x7fffffffULL) return plan_fail(WEFQ_EINVAL, "too many work items");
   std::stable_sort(items.begin(), items.end(),
                    [](const std::pair<double, int64_t>& a, const std::pair<double, int64_t>& b) { return a.first > b.first; });
+  w.codes.resize(items.size());
+  for (size_t i = 0; i < items.size(); ++i) w.codes[i] = items[i].second;
+  return WEFQ_OK;
+}
+
+// Workgroups of the persistent kernel resident per compute unit at (block, lds), and the
+// compute unit count of the current device.
+static void residency(int mode, int block, size_t lds, int device, int* per_cu, int* cus) {
+  *per_cu = 0;
+  *cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, persistent_kernel(mode), block, lds) != hipSuccess ||
+      *per_cu < 1)
+    *per_cu = 1;
+  if (hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || *cus < 1) *cus = 1;
+}
+
+extern "C" {
+
+wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t block, void* stream,
+                             wefq_plan* out) {
+  if (!out || !segs || nseg <= 0) return plan_fail(WEFQ_EINVAL, "plan needs at least one segment and an output");
+  *out = nullptr;
+  if (block != 256 && block != 512) return plan_fail(WEFQ_EINVAL, "block must be 256 or 512");
+  WorkList w;
+  std::vector<int64_t> seg_tiles;
+  std::vector<double> seg_cost;
+  std::vector<int> seg_units;
+  wefq_status st = describe_segments(nseg, segs, w, seg_tiles, seg_cost, seg_units);
+  if (st != WEFQ_OK) return st;
+  const int mode = w.mode, device = w.device;
+  const size_t lds = w.lds;
+  if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
+  const void* k = persistent_kernel(mode);
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
+  int per_cu = 0, cus = 0;
+  residency(mode, block, lds, device, &per_cu, &cus);
+  st = make_items(w, seg_tiles, seg_cost, seg_units, per_cu * cus);
+  if (st != WEFQ_OK) return st;
+  const std::vector<SegDesc>& descs = w.descs;
+  const std::vector<int64_t>& codes = w.codes;
   wefq_plan_s* pl = new (std::nothrow) wefq_plan_s();
   if (!pl) return plan_fail(WEFQ_ENOMEM, "host allocation failed");
-  pl->device = device; pl->mode = mode; pl->block = block; pl->lds = lds; pl->nitems = (int)items.size();
-  std::vector<int64_t> codes(items.size());
-  for (size_t i = 0; i < items.size(); ++i) codes[i] = items[i].second;
+  pl->device = device; pl->mode = mode; pl->block = block; pl->lds = lds; pl->nitems = (int)codes.size();
   bool ok = hipMalloc(&pl->d_segs, sizeof(SegDesc) * nseg) == hipSuccess &&
             hipMalloc(&pl->d_items, sizeof(int64_t) * std::max<size_t>(1, codes.size())) == hipSuccess &&
             hipMalloc(&pl->d_counter, sizeof(int) * 64) == hipSuccess;
@@ -267,6 +321,158 @@ wefq_status wefq_plan_destroy(wefq_plan p) {
   if (!p) return plan_fail(WEFQ_EINVAL, "null plan");
   (void)hipSetDevice(p->device);
   plan_free(p);
+  return WEFQ_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- runners (continuous batching)
+//
+// A runner launches one persistent kernel per call over whatever segments the caller hands
+// it: the serving loop's scheduling tick.  Its work lists go through a ring of slots, each a
+// device buffer of descriptors, items and counter with a pinned host staging copy; a slot is
+// reused once the event recorded after its last launch has completed, so the host waits only
+// when every slot is still in flight.  Nothing is allocated per launch.
+
+namespace {
+constexpr int kRunnerSlots = 4;
+
+struct RunnerSlot {
+  SegDesc* d_segs = nullptr;
+  int64_t* d_items = nullptr;
+  int* d_counter = nullptr;
+  SegDesc* h_segs = nullptr;       // pinned staging
+  int64_t* h_items = nullptr;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+}  // namespace
+
+struct wefq_runner_s {
+  int device = 0;
+  int mode = 0;
+  int block = 512;
+  int max_items = 0, max_segments = 0;
+  int next = 0;
+  int64_t launches = 0;
+  RunnerSlot slots[kRunnerSlots];
+};
+
+static void runner_free(wefq_runner_s* r) {
+  if (!r) return;
+  for (RunnerSlot& sl : r->slots) {
+    if (sl.done) {
+      (void)hipEventSynchronize(sl.done);
+      (void)hipEventDestroy(sl.done);
+    }
+    if (sl.d_segs) (void)hipFree(sl.d_segs);
+    if (sl.d_items) (void)hipFree(sl.d_items);
+    if (sl.d_counter) (void)hipFree(sl.d_counter);
+    if (sl.h_segs) (void)hipHostFree(sl.h_segs);
+    if (sl.h_items) (void)hipHostFree(sl.h_items);
+  }
+  delete r;
+}
+
+extern "C" {
+
+wefq_status wefq_runner_create(int32_t device, int32_t precision, int32_t max_segments, int32_t max_items,
+                               int32_t block, wefq_runner* out) {
+  if (!out) return plan_fail(WEFQ_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (precision != WEFQ_FP32 && precision != WEFQ_BF16X3 && precision != WEFQ_FP64)
+    return plan_fail(WEFQ_EINVAL, "runner precision must be FP32, BF16X3 or FP64");
+  if (block != 256 && block != 512) return plan_fail(WEFQ_EINVAL, "block must be 256 or 512");
+  if (max_segments < 1 || max_segments >= (1 << 15) || max_items < 1)
+    return plan_fail(WEFQ_EINVAL, "max_segments must be in [1, 32767] and max_items >= 1");
+  if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EINVAL, "bad device ordinal");
+  wefq_runner_s* r = new (std::nothrow) wefq_runner_s();
+  if (!r) return plan_fail(WEFQ_ENOMEM, "host allocation failed");
+  r->device = device;
+  r->mode = precision == WEFQ_FP64 ? 2 : (precision == WEFQ_BF16X3 ? 1 : 0);
+  r->block = block;
+  r->max_items = max_items;
+  r->max_segments = max_segments;
+  bool ok = true;
+  for (RunnerSlot& sl : r->slots) {
+    ok = ok && hipMalloc(&sl.d_segs, sizeof(SegDesc) * max_segments) == hipSuccess &&
+         hipMalloc(&sl.d_items, sizeof(int64_t) * max_items) == hipSuccess &&
+         hipMalloc(&sl.d_counter, sizeof(int) * 64) == hipSuccess &&
+         hipHostMalloc(&sl.h_segs, sizeof(SegDesc) * max_segments, hipHostMallocDefault) == hipSuccess &&
+         hipHostMalloc(&sl.h_items, sizeof(int64_t) * max_items, hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+    if (!ok) break;
+  }
+  if (!ok) { runner_free(r); return plan_fail(WEFQ_ENOMEM, "runner allocation failed"); }
+  // the largest tile any core may bring: reserve the device's usable LDS once
+  int dev_lds = 0;
+  if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || dev_lds <= 0)
+    dev_lds = 65536;
+  const int limit = std::min(dev_lds, 163840) - 512;
+  if (hipFuncSetAttribute(persistent_kernel(r->mode), hipFuncAttributeMaxDynamicSharedMemorySize, limit) != hipSuccess) {
+    runner_free(r);
+    return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
+  }
+  *out = r;
+  return WEFQ_OK;
+}
+
+wefq_status wefq_runner_launch(wefq_runner r, int32_t nseg, const wefq_segment* segs, void* stream) {
+  if (!r) return plan_fail(WEFQ_EINVAL, "null runner");
+  if (nseg < 0 || nseg > r->max_segments) return plan_fail(WEFQ_EINVAL, "segment count outside [0, max_segments]");
+  if (nseg == 0) return WEFQ_OK;
+  WorkList w;
+  std::vector<int64_t> seg_tiles;
+  std::vector<double> seg_cost;
+  std::vector<int> seg_units;
+  wefq_status st = describe_segments(nseg, segs, w, seg_tiles, seg_cost, seg_units);
+  if (st != WEFQ_OK) return st;
+  if (w.device != r->device) return plan_fail(WEFQ_EINVAL, "segments must use cores on the runner's device");
+  if (w.mode != r->mode) return plan_fail(WEFQ_EINVAL, "segments must use the runner's precision");
+  if (hipSetDevice(r->device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
+  int per_cu = 0, cus = 0;
+  residency(r->mode, r->block, w.lds, r->device, &per_cu, &cus);
+  st = make_items(w, seg_tiles, seg_cost, seg_units, per_cu * cus);
+  if (st != WEFQ_OK) return st;
+  const int nitems = (int)w.codes.size();
+  if (nitems > r->max_items) return plan_fail(WEFQ_EBUDGET, "the batch has more work items than the runner holds");
+  if (nitems == 0) return WEFQ_OK;
+  RunnerSlot& sl = r->slots[r->next];
+  if (sl.used && hipEventSynchronize(sl.done) != hipSuccess)
+    return plan_fail(WEFQ_EHIP, "waiting for a runner slot failed");
+  std::memcpy(sl.h_segs, w.descs.data(), sizeof(SegDesc) * nseg);
+  std::memcpy(sl.h_items, w.codes.data(), sizeof(int64_t) * nitems);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(sl.d_segs, sl.h_segs, sizeof(SegDesc) * nseg, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(sl.d_items, sl.h_items, sizeof(int64_t) * nitems, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, s, sl.d_counter);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    PlanParams pp{sl.d_segs, sl.d_items, nitems, sl.d_counter};
+    const int grid = std::max(1, std::min(per_cu * cus, nitems));
+    switch (r->mode) {
+      case 0: hipLaunchKernelGGL(apply_persistent_kernel<0>, dim3(grid), dim3(r->block), w.lds, s, pp); break;
+      case 1: hipLaunchKernelGGL(apply_persistent_kernel<1>, dim3(grid), dim3(r->block), w.lds, s, pp); break;
+      default: hipLaunchKernelGGL(apply_persistent_kernel<2>, dim3(grid), dim3(r->block), w.lds, s, pp); break;
+    }
+    e = hipGetLastError();
+  }
+  // the slot is busy until everything enqueued above has run (also after a failed enqueue)
+  const hipError_t er = hipEventRecord(sl.done, s);
+  sl.used = er == hipSuccess;
+  r->next = (r->next + 1) % kRunnerSlots;
+  if (e != hipSuccess) return plan_fail(WEFQ_EHIP, std::string("runner launch failed: ") + hipGetErrorString(e));
+  if (er != hipSuccess) return plan_fail(WEFQ_EHIP, "runner event record failed");
+  ++r->launches;
+  return WEFQ_OK;
+}
+
+wefq_status wefq_runner_destroy(wefq_runner r) {
+  if (!r) return plan_fail(WEFQ_EINVAL, "null runner");
+  (void)hipSetDevice(r->device);
+  runner_free(r);
   return WEFQ_OK;
 }
 

@@ -5,7 +5,7 @@ import pytest
 from gpu_common import dev, say, torch
 
 import paper_2605_28475_amd as wefq
-from paper_2605_28475_amd import autotune, synth
+from paper_2605_28475_amd import _lib, autotune, synth
 
 pytestmark = pytest.mark.gpu
 
@@ -112,3 +112,53 @@ def test_plan_with_anisotropic_cores():
             assert torch.equal(q, r), f"replay {replay}"
     plan.close()
     aniso.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_runner_launches_match_single_segment_applies(prec):
+    """wefq_runner_launch: one persistent launch per call over a changing mix of segments,
+    six calls in a row (every ring slot reused), bitwise equal to standalone applies."""
+    say(f"[runner] {prec}")
+    segs = segments(prec, MIX if prec == "fp32" else MIX[:4])
+    refs = [c.apply_Q(f, precision=prec).clone() for c, f, _ in segs]
+    run = wefq.Runner(0, prec, max_segments=64, max_items=1 << 16)
+    stream = torch.cuda.current_stream(dev())
+    for call in range(6):
+        # a different subset and different cell ranges each call
+        pick = [i for i in range(len(segs)) if (i + call) % 3 != 0]
+        for i in pick:
+            segs[i][2].fill_(float("nan"))
+        parts = []
+        for i in pick:
+            c, f, q = segs[i]
+            cut = (call * 5) % max(1, f.shape[0])
+            parts += [(c, f[:cut], q[:cut]), (c, f[cut:], q[cut:])] if 0 < cut < f.shape[0] else [(c, f, q)]
+        run.launch(parts, stream=stream)
+        torch.cuda.synchronize()
+        for i in pick:
+            assert torch.equal(segs[i][2], refs[i]), (call, i)
+    run.launch([], stream=stream)                         # nothing to do
+    small = wefq.Runner(0, prec, max_segments=4, max_items=2)
+    c, f, q = segs[2]
+    with pytest.raises(wefq.WefqError) as err:
+        small.launch([(c, f, q)], stream=stream)          # more work items than the runner holds
+    assert err.value.status == _lib.WEFQ_EBUDGET
+    with pytest.raises(ValueError):
+        small.launch([(c, f, q)] * 5, stream=stream)      # more segments than it holds
+    small.close()
+    run.close()
+
+
+def test_plan_autotuner_times_whole_plans_and_keeps_results():
+    """autotune.tune_plan picks shapes by timing whole plans; the chosen plan's results equal
+    standalone applies bitwise, and the default shapes are among the candidates."""
+    segs = segments("fp32", [("hs", 4, None, 64), ("vhs", 8, 0.5, 40), ("hs", 12, None, 33)])
+    refs = [c.apply_Q(f).clone() for c, f, _ in segs]
+    slots, block, tried = autotune.tune_plan(segs, "fp32", reps=2)
+    assert block in (256, 512) and len(slots) == len(segs)
+    assert "block=512 slots=0,0,0" in tried and np.isfinite(min(tried.values()))
+    plan = wefq.Plan([(c, f, q, s) for (c, f, q), s in zip(segs, slots)], precision="fp32", block=block)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (c, f, q), r in zip(segs, refs):
+        assert torch.equal(q, r)
