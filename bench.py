@@ -25,7 +25,6 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_apply_fp32_K12L12_B65536.json")
 KERNEL_SOURCES = ["paper_2605_28475_amd/csrc/apply_tile.h", "paper_2605_28475_amd/csrc/apply.hip",
                   "paper_2605_28475_amd/csrc/capi.cpp"]
 
@@ -39,18 +38,102 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE passes recorded under
-    profiles/ (scaled by a plain copy of known size), or None when the kernel
-    sources changed since the counters were taken."""
+def measured_traffic(workload, precision="fp32", K=12, L=12, cells=65536):
+    """HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE passes recorded under profiles/
+    by `--workload traffic` (each scaled by a plain copy of known size), or None when the
+    kernel sources changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(traffic_file(precision, K, L, cells)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("workload") != workload or rec.get("source_hash") != kernel_source_hash():
         return None
     return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def profile_workload(args):
+    model = args.model
+    g = {"hs": 1.0, "mm": 0.0}.get(model, args.gamma)
+    name = f"{model}{g:g}_K{args.K}L{args.L}_B{args.cells}" if model == "vhs" else f"{model}_K{args.K}L{args.L}_B{args.cells}"
+    return name, g
+
+
+def traffic_file(precision, K, L, cells):
+    return os.path.join(ROOT, "profiles", f"traffic_apply_{precision}_K{K}L{L}_B{cells}.json")
+
+
+def profile_run(args, torch, wefq, synth):
+    """A few launches of one apply and one plain copy of f: the program that the rocprofv3
+    counter passes run (the copy moves a known byte count, which scales the counters)."""
+    name, gamma = profile_workload(args)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    core = wefq.Core(args.model, args.K, args.L, gamma=gamma, device=0, precisions=(args.precision,))
+    dt = torch.float64 if args.precision == "fp64" else torch.float32
+    f = torch.tensor(synth.perturbed_maxwellian(args.K, args.L, args.cells, seed=synth.BASE_SEED + 3), dtype=dt,
+                     device=dev)
+    q = torch.empty_like(f)
+    dst = torch.empty_like(f)
+    dst.copy_(f)                                   # calibration: f.numel() * elem bytes read and written
+    ms, _ = time_steps(lambda: core.apply_Q(f, out=q, precision=args.precision), args.launches, stream, torch)
+    print(json.dumps({"workload": name, "precision": args.precision, "launches": args.launches,
+                      "kernel_ms": float(np.mean(ms)), "copy_bytes": f.numel() * f.element_size(),
+                      "algorithmic_bytes_per_launch": 2 * f.numel() * f.element_size(),
+                      "source_hash": kernel_source_hash()}), flush=True)
+    core.close()
+
+
+def _counter_rows(folder, counter):
+    """(kernel name, dispatch id, value) per dispatch from a rocprofv3 counter-collection CSV
+    (values summed over the rows of one dispatch and counter)."""
+    import csv
+    import glob
+    paths = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not paths:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    agg = {}
+    for path in paths:
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (row["Kernel_Name"], row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                agg[key] = agg.get(key, 0.0) + float(row["Counter_Value"])
+    return [(k[0], k[1], v) for k, v in agg.items()]
+
+
+def traffic_from_counters(args):
+    """HBM bytes per launch of the apply kernel from the FETCH_SIZE and WRITE_SIZE passes of a
+    profile run, each scaled by what the same counter reads for the plain copy of f (its bytes
+    are known), written to profiles/traffic_apply_<precision>_K<K>L<L>_B<cells>.json."""
+    name, _ = profile_workload(args)
+    elem = 8 if args.precision == "fp64" else 4
+    N = (args.K + 1) * (args.L + 1) ** 2
+    copy_bytes = args.cells * N * elem
+    out = {"kernel": f"apply_mfma_kernel ({args.precision})", "workload": name, "precision": args.precision,
+           "source_hash": kernel_source_hash(), "algorithmic_bytes_per_launch": 2 * copy_bytes}
+    for counter, folder, key in (("FETCH_SIZE", args.fetch_dir, "fetch"), ("WRITE_SIZE", args.write_dir, "write")):
+        rows = _counter_rows(folder, counter)
+        apply_kib = [v for k, _, v in rows if "apply_mfma_kernel" in k]
+        copy_kib = [v for k, _, v in rows if "apply" not in k and "copy" in k.lower()]
+        if not apply_kib or not copy_kib:
+            raise SystemExit(f"{counter}: apply or copy dispatch missing in {folder}")
+        scale = copy_bytes / (max(copy_kib) * 1024.0)
+        out[f"{key}_kib_per_launch"] = float(np.mean(apply_kib))
+        out[f"{key}_copy_kib"] = float(max(copy_kib))
+        out[f"{key}_scale"] = scale
+        out[f"{key}_bytes_per_launch"] = float(np.mean(apply_kib)) * 1024.0 * scale
+    out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    out["traffic_over_algorithmic"] = out["traffic_bytes_per_launch"] / out["algorithmic_bytes_per_launch"]
+    out["commands"] = [
+        f"rocprofv3 --pmc {c} --kernel-trace --output-format csv -d <out>/{d} -o run -- python3 bench.py "
+        f"--workload profile --model {args.model} --K {args.K} --L {args.L} --cells {args.cells} "
+        f"--precision {args.precision}" for c, d in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write"))]
+    path = traffic_file(args.precision, args.K, args.L, args.cells)
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
 
 
 def log(msg):
@@ -154,14 +237,25 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64/BF16x3 comparison legs")
-    ap.add_argument("--workload", choices=["k12", "uneven", "serve", "rk", "jvp", "build", "orderings"],
+    ap.add_argument("--workload", choices=["k12", "uneven", "serve", "rk", "jvp", "build", "orderings", "profile",
+                                           "traffic"],
                     default="k12",
                     help="k12: the headline batch; uneven: one persistent launch over a mix of cores; "
                          "serve: continuous-batching server under Poisson arrivals; "
                          "rk: batched RK4 time stepping (anisotropic stress relaxation, hard spheres); "
                          "jvp: Jacobian-vector products J(c) d on the headline batch; "
                          "build: radial core build times, isotropic and with angular factors, and reload; "
-                         "orderings: naive, radial-first and angular-first FP64 at K = 4, L = 2..13")
+                         "orderings: naive, radial-first and angular-first FP64 at K = 4, L = 2..13; "
+                         "profile: a few launches of one apply (--K --L --cells --precision) and a plain "
+                         "copy of f, the command to run under rocprofv3 counter passes; "
+                         "traffic: HBM bytes per launch from the FETCH_SIZE and WRITE_SIZE passes "
+                         "(--fetch-dir, --write-dir) of a profile run, written to profiles/ (no GPU)")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"],
+                    help="profile/traffic: the apply precision")
+    ap.add_argument("--launches", type=int, default=2, help="profile: launches of the apply")
+    ap.add_argument("--model", default="vhs", help="profile/traffic: collision model (gamma from --gamma)")
+    ap.add_argument("--fetch-dir", default=None, help="traffic: output folder of the FETCH_SIZE pass")
+    ap.add_argument("--write-dir", default=None, help="traffic: output folder of the WRITE_SIZE pass")
     ap.add_argument("--tick-ms", type=float, default=16.0, help="serve: work per scheduling tick, in ms")
     ap.add_argument("--serve-depth", type=int, default=2, help="serve: launches in flight")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=None, help="serve: arrival rates (req/s)")
@@ -173,9 +267,13 @@ def main():
               "GPUs, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "traffic":
+        return traffic_from_counters(args)
     import torch
     import paper_2605_28475_amd as wefq
     from paper_2605_28475_amd import synth
+    if args.workload == "profile":
+        return profile_run(args, torch, wefq, synth)
     if args.workload == "uneven":
         return bench_uneven(args, torch, wefq, synth)
     if args.workload == "serve":
@@ -248,7 +346,7 @@ def main():
                    "precision": "fp32 coupling + fp32 MFMA contraction"},
         "p50_ms": float(np.percentile(kms, 50)), "p99_ms": float(np.percentile(kms, 99)),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp32"], "traffic": measured_traffic(workload),
+                     "frac": achieved / PEAK["fp32"], "traffic": measured_traffic(workload, "fp32", K, L, B),
                      "flop_per_cell": flop_cell, "kernel_ms": float(np.mean(kms)),
                      "algorithmic_bytes": 2.0 * B * N * 4},
         "conservation_max_abs": check["max"],

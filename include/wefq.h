@@ -88,6 +88,10 @@ typedef struct {
   int32_t device;         /* HIP device ordinal */
   int32_t n_beta;         /* 0 <= n_beta <= WEFQ_MAX_BETA; finite coefficients */
   const double* beta;     /* host pointer, n_beta doubles (Legendre coefficients) */
+  int32_t rad_pad;        /* 0 <= pad <= 64 extra points in each radial Gauss rule, and */
+  int32_t ang_pad;        /* in each angular one, beyond the counts that are exact for the
+                             polynomial degree of the integrand (Sections 3.3 and 5.1: padding
+                             for the self-convergence study); 0 is the exact rule */
 } wefq_core_desc;
 
 typedef struct {
@@ -103,6 +107,7 @@ typedef struct {
   double beta[WEFQ_MAX_BETA];
   int64_t radial_groups;  /* distinct (channel, q2, q3) triples of the table when the
                              radial-first tables are prepared, else 0 */
+  int64_t rad_pad, ang_pad; /* quadrature padding of the build (0 for a core loaded from file) */
 } wefq_core_info;
 
 /* Build the radial core R (Sections 3.2-3.3, 4.3-4.4) on the GPU in FP64 and the

@@ -46,10 +46,11 @@ class Core:
     """A built radial core (wefq_build_core) resident on one GPU.
 
     beta: Legendre coefficients of the angular factor of B(u, cos chi) = b0 u^gamma
-    beta(cos chi), or None for the isotropic kernel."""
+    beta(cos chi), or None for the isotropic kernel.  rad_pad, ang_pad: extra points in the
+    radial and angular Gauss rules beyond the exact counts (self-convergence studies)."""
 
     def __init__(self, model, K, L, gamma=None, b0=0.0, precisions=("fp64", "fp32", "bf16x3"),
-                 device=0, stream=None, beta=None):
+                 device=0, stream=None, beta=None, rad_pad=0, ang_pad=0):
         m = MODELS[model] if isinstance(model, str) else int(model)
         if gamma is None:
             gamma = {MAXWELL: 0.0, HARD_SPHERE: 1.0}.get(m, 0.5)
@@ -59,7 +60,8 @@ class Core:
         coef = [] if beta is None else [float(b) for b in beta]
         arr = (ctypes.c_double * max(1, len(coef)))(*coef)
         desc = _lib.CoreDesc(m, float(gamma), float(b0), int(K), int(L), mask, int(device),
-                             len(coef), ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)) if coef else None)
+                             len(coef), ctypes.cast(arr, ctypes.POINTER(ctypes.c_double)) if coef else None,
+                             int(rad_pad), int(ang_pad))
         h = ctypes.c_void_p()
         _lib.check(_lib.lib().wefq_build_core(ctypes.byref(desc), _stream_ptr(stream, device), ctypes.byref(h)))
         self._adopt(h, device)

@@ -21,7 +21,8 @@ class CoreDesc(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("gamma", ctypes.c_double), ("b0", ctypes.c_double),
                 ("Kmax", ctypes.c_int32), ("Lmax", ctypes.c_int32),
                 ("precisions", ctypes.c_uint32), ("device", ctypes.c_int32),
-                ("n_beta", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double))]
+                ("n_beta", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double)),
+                ("rad_pad", ctypes.c_int32), ("ang_pad", ctypes.c_int32)]
 
 
 class CoreInfo(ctypes.Structure):
@@ -32,7 +33,7 @@ class CoreInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("flop_alg_per_cell", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("b0", ctypes.c_double), ("model", ctypes.c_int64),
                 ("n_beta", ctypes.c_int64), ("beta", ctypes.c_double * MAX_BETA),
-                ("radial_groups", ctypes.c_int64)]
+                ("radial_groups", ctypes.c_int64), ("rad_pad", ctypes.c_int64), ("ang_pad", ctypes.c_int64)]
 
 
 class Segment(ctypes.Structure):

@@ -81,6 +81,10 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   constexpr int U = (HH + 7) / 8;
   constexpr int GQ = gq_for(H);
   constexpr int NP = GQ / SLOTS > 0 ? GQ / SLOTS : 1;
+  // The two-buffer coupling pipeline (below) where it was measured faster: FP32 at quadrants
+  // of 6 to 8 and BF16x3 from 6 up, one input.  It costs 3H (pairs) more registers, which
+  // spill in FP64 and in FP32 at 9x9, and costs occupancy below 6x6.
+  constexpr bool PIPE = !TWO && ((MODE == 0 && H >= 6 && H <= 8) || (MODE == 1 && H >= 6));
   T* fs = reinterpret_cast<T*>(lds_raw);
   int& unit_ctr = *unit_ctr_p;
   T* Qo = static_cast<T*>(p.Q);
@@ -141,6 +145,13 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   cu32* mq = (cu32*)(pd ? p.mq_pad : p.mq);
   cf32* mg = (cf32*)p.mg;
   cf64* mg64 = (cf64*)p.mg64;
+  // the same rows through vector loads: an offset the compiler cannot prove uniform (a zero
+  // produced by a register move it cannot see through) makes every access a vector load
+  int vz;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+  const uint32_t* vmq = (pd ? p.mq_pad : p.mq) + vz;
+  const float* vmg = p.mg + vz;
+  const double* vmg64 = p.mg64 + vz;
   while (true) {
     int u = 0;
     if (lane == 0) u = atomicAdd(&unit_ctr, 1);
@@ -193,6 +204,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
         // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.  With two inputs c, d (the
         // Jacobian-vector product) each product x (x) y becomes c_x (x) d_y + d_x (x) c_y.
         auto weight = [&](int e) -> T { return MODE == 2 ? (T)mg64[e] : (T)mg[e]; };
+        auto vweight = [&](int e) -> T { return MODE == 2 ? (T)vmg64[e] : (T)vmg[e]; };
         auto gather = [&](uint32_t qa, uint32_t qb, Rows<T, H, TWO>& x, bool pair) {
           const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
           const T* pa = lane_w + (int)(qa >> 16) * TB;
@@ -237,7 +249,98 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
             outer_product<H>(phi, uu, x.a);
           }
         };
-        if constexpr (SLOTS == 1) {     // the slice is shared by the whole wave
+        // Software pipeline over the slice's rows: two row buffers, A and B, alternate, so
+        // that while one accumulates its outer product the LDS gathers of the other are in
+        // flight (the loops are unrolled by two rows or pairs, with scheduling barriers that
+        // keep each gather ahead of the previous row's arithmetic).  The routing rows (offsets
+        // and weights) come through vector loads two rows ahead: a scalar load there would
+        // share the LDS counter, and every wait for it would also wait for all gathers in
+        // flight.  The arrays carry 8 entries of tail slack (row offset 0, weight 0).
+        // rows: number of rows (or pairs) of this lane's slice; fetch(i, qa, qb, ga, gb):
+        // routing of row i of it (zero weight past its end); pair: two rows per step.
+        auto pipeline = [&](int rows, int maxrows, auto fetch, bool pair) {
+          if (maxrows <= 0) return;
+          uint32_t qa0, qb0, qa1, qb1;
+          T ga0, gb0, ga1, gb1;
+          fetch(0, qa0, qb0, ga0, gb0);
+          fetch(1, qa1, qb1, ga1, gb1);
+          Rows<T, H, TWO> A, B;
+          gather(qa0, qb0, A, pair);
+          int i = 0;
+          for (; i + 1 < maxrows; i += 2) {
+            uint32_t qa2, qb2, qa3, qb3;
+            T ga2, gb2, ga3, gb3;
+            fetch(i + 2, qa2, qb2, ga2, gb2);
+            gather(qa1, qb1, B, pair);
+            __builtin_amdgcn_sched_barrier(0);
+            if (pair) pair_acc(ga0, gb0, A); else single_acc(ga0, A);
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(i + 3, qa3, qb3, ga3, gb3);
+            gather(qa2, qb2, A, pair);
+            __builtin_amdgcn_sched_barrier(0);
+            if (pair) pair_acc(ga1, gb1, B); else single_acc(ga1, B);
+            __builtin_amdgcn_sched_barrier(0);
+            ga0 = ga2; gb0 = gb2; ga1 = ga3; gb1 = gb3; qa1 = qa3; qb1 = qb3;
+          }
+          if (i < maxrows) {
+            if (pair) pair_acc(ga0, gb0, A); else single_acc(ga0, A);
+          }
+          (void)rows;
+        };
+        if constexpr (PIPE && SLOTS == 1) {     // the slice is shared by the whole wave
+          const int s = soff + units[ub + 2 + gi];
+          const int e0 = sptr[s], e1 = sptr[s + 1], ep = spair[s];
+          const int np_ = (ep - e0) >> 1, ns_ = e1 - ep;
+          pipeline(np_, np_, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            const int e = e0 + 2 * i;   // within the table's slack for i <= np_ + 1
+            qa = vmq[e]; qb = vmq[e + 1]; ga = vweight(e); gb = vweight(e + 1);
+          }, true);
+          pipeline(ns_, ns_, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            const int e = ep + i;
+            qa = vmq[e]; qb = 0u; ga = vweight(e); gb = T(0);
+          }, false);
+        } else if constexpr (PIPE) {
+          // Lanes of different output states walk different slices: every lane fetches its
+          // own slot's rows (lane-varying addresses, vector loads); the loops run to the
+          // longest slot, and rows past a slot's end carry weight zero and row offset 0.
+          int se0[SLOTS], sep[SLOTS], se1[SLOTS];
+          int maxp = 0, maxs = 0;
+#pragma unroll
+          for (int sl = 0; sl < SLOTS; ++sl) {
+            const int qs = gi * SLOTS + sl;
+            se0[sl] = se1[sl] = sep[sl] = 0;
+            if (qs < nq) {
+              const int ss = soff + units[ub + 2 + qs];
+              se0[sl] = sptr[ss];
+              se1[sl] = sptr[ss + 1];
+              sep[sl] = spair[ss];
+            }
+            const int np_s = (sep[sl] - se0[sl]) >> 1, ns_s = se1[sl] - sep[sl];
+            maxp = maxp > np_s ? maxp : np_s;
+            maxs = maxs > ns_s ? maxs : ns_s;
+          }
+          int my0 = 0, myp = 0, my1 = 0;
+#pragma unroll
+          for (int sl = 0; sl < SLOTS; ++sl)
+            if (slot == sl) { my0 = se0[sl]; myp = sep[sl]; my1 = se1[sl]; }
+          const int my_np = (myp - my0) >> 1, my_ns = my1 - myp;
+          pipeline(my_np, maxp, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            const bool in = i < my_np;
+            const int e = in ? my0 + 2 * i : my0;     // a valid index past the end
+            const uint32_t xa = vmq[e], xb = vmq[e + 1];
+            const T ya = vweight(e), yb = vweight(e + 1);
+            qa = in ? xa : 0u; qb = in ? xb : 0u; ga = in ? ya : T(0); gb = in ? yb : T(0);
+          }, true);
+          pipeline(my_ns, maxs, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            const bool in = i < my_ns;
+            const int e = in ? myp + i : myp;
+            const uint32_t xa = vmq[e];
+            const T ya = vweight(e);
+            qa = in ? xa : 0u; qb = 0u; ga = in ? ya : T(0); gb = T(0);
+          }, false);
+        } else if constexpr (SLOTS == 1) {
+          // Without the two row buffers (where registers do not allow them): one row's
+          // gathers ahead, routing rows through scalar loads
           const int s = soff + units[ub + 2 + gi];
           const int e0 = sptr[s], e1 = sptr[s + 1], ep = spair[s];
           // software pipeline: the gathers of the next row (pair) are in flight

@@ -515,9 +515,13 @@ wefq_status wefq_build_core(const wefq_core_desc* desc, void* stream, wefq_handl
     *out = nullptr;
     wefq_core* h = nullptr;
     std::vector<CooRow> coo;
+    if (desc->rad_pad < 0 || desc->rad_pad > 64 || desc->ang_pad < 0 || desc->ang_pad > 64)
+      return fail(WEFQ_EINVAL, "rad_pad and ang_pad must lie in [0, 64]");
     wefq_status st = new_core(desc->model, desc->gamma, desc->b0, desc->Kmax, desc->Lmax, desc->precisions,
                               desc->device, desc->n_beta, desc->beta, &h, coo);
     if (st != WEFQ_OK) return st;
+    h->rad_pad = desc->rad_pad;
+    h->ang_pad = desc->ang_pad;
     hipStream_t s = (hipStream_t)stream;
     if (!build_radial_core(h, coo, s)) { free_core(h); return WEFQ_EHIP; }
     return finish_core(h, coo, s, out);
@@ -542,6 +546,8 @@ wefq_status wefq_core_info_get(wefq_handle h, wefq_core_info* info) {
   info->n_beta = (int64_t)h->beta.size();
   for (int j = 0; j < WEFQ_MAX_BETA; ++j) info->beta[j] = j < (int)h->beta.size() ? h->beta[j] : 0.0;
   info->radial_groups = h->rad_groups;
+  info->rad_pad = h->rad_pad;
+  info->ang_pad = h->ang_pad;
   return WEFQ_OK;
 }
 

@@ -369,9 +369,11 @@ static void launch_accumulate(int NK, int NT, hipStream_t stream, const ChanPara
 bool build_radial_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t stream) {
   const int K = h->K, L = h->L, NK = h->NK, NT = h->NT;
   const int D = 2 * K + L;
-  const int nsig = (3 * D) / 2 / 2 + 1;
-  const int nmu = (3 * D) / 2 + 1;
-  const int nnu = (K + L) / 2 + 1;
+  // point counts exact for the polynomial degree 3D of the integrand (Section 3.3), plus the
+  // caller's padding: rad_pad more points in each radial rule, ang_pad more in each angular one
+  const int nsig = (3 * D) / 2 / 2 + 1 + h->rad_pad;
+  const int nmu = (3 * D) / 2 + 1 + h->ang_pad;
+  const int nnu = (K + L) / 2 + 1 + h->ang_pad;
   std::vector<double> xs, ws, xu, wu, xm, wm, xn, wn;
   gauss_rule(1, nsig, 0.5, xs, ws);                  // sigma = G^2, weight sigma^{1/2} e^{-sigma}
   gauss_rule(1, nsig, 0.5 * (1.0 + h->gamma), xu, wu); // s = u^2/4, weight s^{(1+gamma)/2} e^{-s}
@@ -384,7 +386,7 @@ bool build_radial_core(wefq_core* h, const std::vector<CooRow>& coo, hipStream_t
   // azimuths (exact for trigonometric degree D)
   const bool angular = !h->beta.empty();
   const int J = angular ? (int)h->beta.size() - 1 : 0;
-  const int nt = angular ? (D + J) / 2 + 1 : 0, ne = angular ? D + 1 : 0;
+  const int nt = angular ? (D + J) / 2 + 1 + h->ang_pad : 0, ne = angular ? D + 1 + h->ang_pad : 0;
   std::vector<double> tt, wt, ce, se;
   double loss_scale = 1.0;                           // int dn beta(u_hat . n) / (4 pi)
   if (angular) {

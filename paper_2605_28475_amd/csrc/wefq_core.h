@@ -20,6 +20,7 @@ struct wefq_core {
   std::vector<double> beta;            // Legendre coefficients of the angular factor; empty: isotropic
   unsigned precisions = 0;
   int64_t quad_nodes = 0;
+  int rad_pad = 0, ang_pad = 0;        // extra Gauss nodes beyond the exact counts (self-convergence)
   int64_t device_bytes = 0;
   std::vector<wefq::Channel> chans;
   std::vector<double> R64;             // host copy, zeroed, [c][k1][k2][k3]

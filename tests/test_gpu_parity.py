@@ -341,3 +341,24 @@ def test_binding_refuses_bad_tensors_before_launch():
         wefq.Plan([(core, f64, torch.empty_like(f64))], precision="fp32")    # dtype of the plan
     torch.cuda.synchronize()
     assert torch.all(good == 5.0)
+
+
+@pytest.mark.parametrize("K,model,gamma,pad", [(4, "hs", 1.0, 32), (4, "mm", 0.0, 32), (12, "vhs", 0.5, 16),
+                                             (16, "hs", 1.0, 16)])
+def test_core_self_convergence_in_padding(K, model, gamma, pad):
+    """Section 5.1 (Fig. 2: the core at K = L = 4 converges to FP64 precision as the rules are
+    padded).  The rules here are exact for the integrand's degree, so extra points in every
+    rule change R only by rounding: sums over 10^4 to 10^5 nodes of terms that cancel, about
+    3e-14 of the core's largest entry at K = L = 12; the bound is 1e-13."""
+    base_core = gpu_core(model, K, K, gamma)
+    base = base_core.download_R()
+    padded = wefq.Core(model, K, K, gamma=gamma, device=0, precisions=("fp64",), rad_pad=pad, ang_pad=pad)
+    assert padded.info["rad_pad"] == pad and padded.info["quad_nodes"] > base_core.info["quad_nodes"]
+    Rp = padded.download_R()
+    padded.close()
+    err = rel_err(Rp, base)
+    per_channel = float(max(np.abs(Rp[c] - base[c]).max() / np.abs(base[c]).max()
+                            for c in range(len(base)) if np.abs(base[c]).max() > 0))
+    say(f"[padding] K=L={K} {model} pad {pad}: max |R_pad - R_0| / max |R_0| = {err:.2e}, "
+        f"worst channel {per_channel:.2e}")
+    assert err < 1e-13

@@ -73,6 +73,10 @@ def test_error_paths_without_device():
     assert b"[0, 16]" in lib.wefq_last_error()
     desc = _lib.CoreDesc(9, 0.0, 0.0, 4, 4, 0, 0)
     assert lib.wefq_build_core(ctypes.byref(desc), None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+    for pads in ((65, 0), (0, -1)):                      # quadrature padding outside [0, 64]
+        desc = _lib.CoreDesc(1, 0.0, 0.0, 4, 4, 0, 0, 0, None, *pads)
+        assert lib.wefq_build_core(ctypes.byref(desc), None, ctypes.byref(h)) == _lib.WEFQ_EINVAL
+        assert b"pad" in lib.wefq_last_error()
     # angular factor: too many coefficients, a null array, a non-finite coefficient
     coef = (ctypes.c_double * 40)(*([1.0] * 40))
     ptr = ctypes.cast(coef, ctypes.POINTER(ctypes.c_double))
