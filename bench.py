@@ -75,7 +75,12 @@ def profile_run(args, torch, wefq, synth):
                      device=dev)
     q = torch.empty_like(f)
     dst = torch.empty_like(f)
-    dst.copy_(f)                                   # calibration: f.numel() * elem bytes read and written
+    # calibration: a copy of f reads and writes f.numel() * elem bytes; 2 GiB written first push
+    # f out of the caches (f was just uploaded, and a cache-resident f would read short)
+    flush = torch.empty(1 << 29, dtype=torch.float32, device=dev)
+    flush.fill_(1.0)
+    del flush
+    dst.copy_(f)
     ms, _ = time_steps(lambda: core.apply_Q(f, out=q, precision=args.precision), args.launches, stream, torch)
     print(json.dumps({"workload": name, "precision": args.precision, "launches": args.launches,
                       "kernel_ms": float(np.mean(ms)), "copy_bytes": f.numel() * f.element_size(),

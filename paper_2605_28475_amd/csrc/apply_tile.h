@@ -11,6 +11,8 @@ namespace wefq {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 
 struct MfmaParams {
   const void* f;
@@ -147,11 +149,13 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   cf64* mg64 = (cf64*)p.mg64;
   // the same rows through vector loads: an offset the compiler cannot prove uniform (a zero
   // produced by a register move it cannot see through) makes every access a vector load
+  // (indexing a uniform base with a lane-varying 32-bit index lets the loads use a scalar base
+  // and a 32-bit vector offset)
+  // (the pipelined loops walk them with running pointers, one add per pointer and step)
   int vz;
   asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
-  const uint32_t* vmq = (pd ? p.mq_pad : p.mq) + vz;
-  const float* vmg = p.mg + vz;
-  const double* vmg64 = p.mg64 + vz;
+  const uint32_t* mqv = (pd ? p.mq_pad : p.mq) + vz;
+  const T* mgv = (MODE == 2 ? reinterpret_cast<const T*>(p.mg64) : reinterpret_cast<const T*>(p.mg)) + vz;
   while (true) {
     int u = 0;
     if (lane == 0) u = atomicAdd(&unit_ctr, 1);
@@ -204,7 +208,6 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
         // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.  With two inputs c, d (the
         // Jacobian-vector product) each product x (x) y becomes c_x (x) d_y + d_x (x) c_y.
         auto weight = [&](int e) -> T { return MODE == 2 ? (T)mg64[e] : (T)mg[e]; };
-        auto vweight = [&](int e) -> T { return MODE == 2 ? (T)vmg64[e] : (T)vmg[e]; };
         auto gather = [&](uint32_t qa, uint32_t qb, Rows<T, H, TWO>& x, bool pair) {
           const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
           const T* pa = lane_w + (int)(qa >> 16) * TB;
@@ -291,13 +294,18 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
           const int s = soff + units[ub + 2 + gi];
           const int e0 = sptr[s], e1 = sptr[s + 1], ep = spair[s];
           const int np_ = (ep - e0) >> 1, ns_ = e1 - ep;
-          pipeline(np_, np_, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
-            const int e = e0 + 2 * i;   // within the table's slack for i <= np_ + 1
-            qa = vmq[e]; qb = vmq[e + 1]; ga = vweight(e); gb = vweight(e + 1);
+          // rows are fetched in order, up to two past the end (within the table's slack)
+          const uint32_t* pq = mqv + e0;
+          const T* pw = mgv + e0;
+          pipeline(np_, np_, [&](int, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            qa = pq[0]; qb = pq[1]; ga = pw[0]; gb = pw[1];
+            pq += 2; pw += 2;
           }, true);
-          pipeline(ns_, ns_, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
-            const int e = ep + i;
-            qa = vmq[e]; qb = 0u; ga = vweight(e); gb = T(0);
+          pq = mqv + ep;
+          pw = mgv + ep;
+          pipeline(ns_, ns_, [&](int, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            qa = pq[0]; qb = 0u; ga = pw[0]; gb = T(0);
+            pq += 1; pw += 1;
           }, false);
         } else if constexpr (PIPE) {
           // Lanes of different output states walk different slices: every lane fetches its
@@ -324,19 +332,25 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
           for (int sl = 0; sl < SLOTS; ++sl)
             if (slot == sl) { my0 = se0[sl]; myp = sep[sl]; my1 = se1[sl]; }
           const int my_np = (myp - my0) >> 1, my_ns = my1 - myp;
+          // each lane's pointers stop at the end of its slot's rows, where they still read
+          // valid table entries (the slot's singles, or the slack); those reads are masked
+          const uint32_t* pq = mqv + my0;
+          const T* pw = mgv + my0;
           pipeline(my_np, maxp, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
             const bool in = i < my_np;
-            const int e = in ? my0 + 2 * i : my0;     // a valid index past the end
-            const uint32_t xa = vmq[e], xb = vmq[e + 1];
-            const T ya = vweight(e), yb = vweight(e + 1);
+            const uint32_t xa = pq[0], xb = pq[1];
+            const T ya = pw[0], yb = pw[1];
             qa = in ? xa : 0u; qb = in ? xb : 0u; ga = in ? ya : T(0); gb = in ? yb : T(0);
+            pq += in ? 2 : 0; pw += in ? 2 : 0;
           }, true);
+          pq = mqv + myp;
+          pw = mgv + myp;
           pipeline(my_ns, maxs, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
             const bool in = i < my_ns;
-            const int e = in ? myp + i : myp;
-            const uint32_t xa = vmq[e];
-            const T ya = vweight(e);
+            const uint32_t xa = pq[0];
+            const T ya = pw[0];
             qa = in ? xa : 0u; qb = 0u; ga = in ? ya : T(0); gb = T(0);
+            pq += in ? 1 : 0; pw += in ? 1 : 0;
           }, false);
         } else if constexpr (SLOTS == 1) {
           // Without the two row buffers (where registers do not allow them): one row's
@@ -497,13 +511,19 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
         } else {
 #pragma unroll
           for (int uu8 = 0; uu8 < U; ++uu8) {
+            // split hi/lo two values at a time: one packed round-to-nearest conversion gives
+            // both hi halves, which are unpacked back to FP32 by a shift and a mask
             v8bf bh, bl;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const float x = phi[uu8 * 8 + e];
-              const __bf16 xh = (__bf16)x;
-              bh[e] = xh;
-              bl[e] = (__bf16)(x - (float)xh);
+            for (int e = 0; e < 8; e += 2) {
+              const float x0 = phi[uu8 * 8 + e], x1 = phi[uu8 * 8 + e + 1];
+              const v2bf h = __builtin_convertvector((v2f){x0, x1}, v2bf);
+              const uint32_t hb = __builtin_bit_cast(uint32_t, h);
+              const float h0 = __builtin_bit_cast(float, hb << 16);
+              const float h1 = __builtin_bit_cast(float, hb & 0xffff0000u);
+              const v2bf l = __builtin_convertvector((v2f){x0 - h0, x1 - h1}, v2bf);
+              bh[e] = h[0]; bh[e + 1] = h[1];
+              bl[e] = l[0]; bl[e + 1] = l[1];
             }
             const int64_t off = (((int64_t)ct * U + uu8) * 64 + lane) * 8;
             const v8bf ah = HOIST ? ahi[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rhi + off);
