@@ -87,6 +87,9 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   // of 6 to 8 and BF16x3 from 6 up, one input.  It costs 3H (pairs) more registers, which
   // spill in FP64 and in FP32 at 9x9, and costs occupancy below 6x6.
   constexpr bool PIPE = !TWO && ((MODE == 0 && H >= 6 && H <= 8) || (MODE == 1 && H >= 6));
+  // Without the pipeline, tiles of several output states per column group fetch each lane's
+  // own routing rows through vector loads (VR) or each slot's rows through scalar loads.
+  constexpr bool VR = !TWO && SLOTS > 1;
   T* fs = reinterpret_cast<T*>(lds_raw);
   int& unit_ctr = *unit_ctr_p;
   T* Qo = static_cast<T*>(p.Q);
@@ -408,7 +411,28 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
             maxp = maxp > np_s ? maxp : np_s;
             maxs = maxs > ns_s ? maxs : ns_s;
           }
+          // VR: every lane fetches its own slot's rows through vector loads, walking
+          // running pointers that stop at the end of the slot's rows (where they still read
+          // valid entries: the slot's singles, or the table's slack) and masking past it;
+          // otherwise each slot's rows come through scalar loads and lanes select theirs
+          int my0 = 0, myp = 0, my1 = 0;
+#pragma unroll
+          for (int sl = 0; sl < SLOTS; ++sl)
+            if (slot == sl) { my0 = se0[sl]; myp = sep[sl]; my1 = se1[sl]; }
+          const int my_np = (myp - my0) >> 1, my_ns = my1 - myp;
+          const uint32_t* pqp = mqv + my0;
+          const T* pwp = mgv + my0;
+          const uint32_t* pqs = mqv + myp;
+          const T* pws = mgv + myp;
           auto fetch_pair = [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+            if constexpr (VR) {
+              const bool in = i < my_np;
+              const uint32_t xa = pqp[0], xb = pqp[1];
+              const T ya = pwp[0], yb = pwp[1];
+              qa = in ? xa : 0u; qb = in ? xb : 0u; ga = in ? ya : T(0); gb = in ? yb : T(0);
+              pqp += in ? 2 : 0; pwp += in ? 2 : 0;
+              return;
+            }
             qa = qb = 0u;
             ga = gb = T(0);
 #pragma unroll
@@ -422,6 +446,14 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
             }
           };
           auto fetch_single = [&](int i, uint32_t& qq, T& gg) {
+            if constexpr (VR) {
+              const bool in = i < my_ns;
+              const uint32_t x = pqs[0];
+              const T y = pws[0];
+              qq = in ? x : 0u; gg = in ? y : T(0);
+              pqs += in ? 1 : 0; pws += in ? 1 : 0;
+              return;
+            }
             qq = 0u;
             gg = T(0);
 #pragma unroll
