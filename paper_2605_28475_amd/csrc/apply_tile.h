@@ -31,11 +31,12 @@ struct MfmaParams {
   const uint32_t* mq_pad;  // the same with the padded row pitch (16-cell tiles with a pad row)
   const float* mg;         // merged weights (FP32 / BF16X3)
   const double* mg64;      // merged weights (FP64)
-  const float* Rt32;       // [NTm][H*H][64]: rows k1 < 16 in the MFMA A-operand layout
-  const double* Rt64;      // [NTm][H*H][64]
+  const float* Rt32;       // [NTm][ceil(H*H/4)][64][4]: rows k1 < 16 in the MFMA A-operand
+                           // layout, 4 steps t per lane and load
+  const double* Rt64;      // [NTm][ceil(H*H/2)][64][2]
   const uint16_t* Rhi;     // [NTm][U][64][8]
   const uint16_t* Rlo;
-  const float* R16_32;     // NK = 17 only: row k1 = 16 of R per lane group, [NTm][4][H*H]
+  const float* R16_32;     // NK = 17 only: row k1 = 16 of R per lane group, [NTm][4][4 ceil(H*H/4)]
   const double* R16_64;
 };
 
@@ -43,6 +44,7 @@ struct MfmaParams {
 __host__ __device__ constexpr int gq_for(int) { return kUnitStates; }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 // MODE 0: FP32 MFMA, 1: split BF16x3 MFMA, 2: FP64 MFMA.
 template <int MODE> struct ModeTraits;
@@ -81,6 +83,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   constexpr int TB = 16 / SLOTS;
   constexpr int HH = H * H;
   constexpr int U = (HH + 7) / 8;
+  constexpr int Q4 = (HH + 3) / 4, Q2 = (HH + 1) / 2;   // vector loads of the A-operand tiles
   constexpr int GQ = gq_for(H);
   constexpr int NP = GQ / SLOTS > 0 ? GQ / SLOTS : 1;
   // The two-buffer coupling pipeline (below) where it was measured faster: FP32 at quadrants
@@ -181,17 +184,25 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
       // registers allow, it is loaded once per channel ahead of the first coupling,
       // so its latency hides behind the VALU work; otherwise it streams in batches.
       constexpr bool HOIST = MODE == 2 ? (H <= 4) : (H <= 7);
-      float a32[HOIST && MODE == 0 ? HH : 1];
-      double a64[HOIST && MODE == 2 ? HH : 1];
+      float a32[HOIST && MODE == 0 ? Q4 * 4 : 1];
+      double a64[HOIST && MODE == 2 ? Q2 * 2 : 1];
       v8bf ahi[HOIST && MODE == 1 ? U : 1], alo[HOIST && MODE == 1 ? U : 1];
       if constexpr (HOIST && MODE == 0) {
-        const float* At = p.Rt32 + ((int64_t)ct * HH) * 64 + lane;
+        const v4f* At = reinterpret_cast<const v4f*>(p.Rt32) + (int64_t)ct * Q4 * 64 + lane;
 #pragma unroll
-        for (int t = 0; t < HH; ++t) a32[t] = At[t * 64];
+        for (int q = 0; q < Q4; ++q) {
+          const v4f x = At[q * 64];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a32[4 * q + i] = x[i];
+        }
       } else if constexpr (HOIST && MODE == 2) {
-        const double* At = p.Rt64 + ((int64_t)ct * HH) * 64 + lane;
+        const v2d* At = reinterpret_cast<const v2d*>(p.Rt64) + (int64_t)ct * Q2 * 64 + lane;
 #pragma unroll
-        for (int t = 0; t < HH; ++t) a64[t] = At[t * 64];
+        for (int q = 0; q < Q2; ++q) {
+          const v2d x = At[q * 64];
+          a64[2 * q] = x[0];
+          a64[2 * q + 1] = x[1];
+        }
       } else if constexpr (HOIST && MODE == 1) {
 #pragma unroll
         for (int uu8 = 0; uu8 < U; ++uu8) {
@@ -517,24 +528,30 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
           for (int t = 0; t < HH; ++t)
             acc[gi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[t], phi[t], acc[gi], 0, 0, 0);
         } else if constexpr (MODE == 0) {
-          const float* At = p.Rt32 + ((int64_t)ct * HH) * 64 + lane;
+          const v4f* At = reinterpret_cast<const v4f*>(p.Rt32) + (int64_t)ct * Q4 * 64 + lane;
 #pragma unroll
           for (int t0 = 0; t0 < HH; t0 += 8) {
             float av[8];
+            const v4f x0 = At[(t0 / 4) * 64];
+            const v4f x1 = (t0 + 4 < HH) ? At[(t0 / 4 + 1) * 64] : (v4f){0, 0, 0, 0};
 #pragma unroll
-            for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0f;
+            for (int t = 0; t < 4; ++t) { av[t] = x0[t]; av[t + 4] = x1[t]; }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < 8; ++t)
               if (t0 + t < HH) acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], phi[t0 + t], acc[gi], 0, 0, 0);
           }
         } else if constexpr (MODE == 2) {
-          const double* At = p.Rt64 + ((int64_t)ct * HH) * 64 + lane;
+          const v2d* At = reinterpret_cast<const v2d*>(p.Rt64) + (int64_t)ct * Q2 * 64 + lane;
 #pragma unroll
           for (int t0 = 0; t0 < HH; t0 += 8) {
             double av[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) av[t] = (t0 + t < HH) ? At[(t0 + t) * 64] : 0.0;
+            for (int t = 0; t < 8; t += 2) {
+              const v2d x = (t0 + t < HH) ? At[((t0 + t) / 2) * 64] : (v2d){0.0, 0.0};
+              av[t] = x[0];
+              av[t + 1] = x[1];
+            }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < 8; ++t)
@@ -570,14 +587,24 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
           // row k1 = 16: partial dot product over this lane group's quadrant, then
           // the four lane groups of a column (lanes j, j+16, j+32, j+48) are summed
           T part = T(0);
+          // (the row is padded to 4 ceil(HH/4) values, so whole vectors load)
           if constexpr (MODE == 2) {
-            const double* r16 = p.R16_64 + ((int64_t)ct * 4 + r) * HH;
+            const v2d* r16 = reinterpret_cast<const v2d*>(p.R16_64 + ((int64_t)ct * 4 + r) * (Q4 * 4));
 #pragma unroll
-            for (int t = 0; t < HH; ++t) part = fma((T)r16[t], phi[t], part);
+            for (int q = 0; q < Q2; ++q) {
+              const v2d x = r16[q];
+              part = fma(x[0], phi[2 * q], part);
+              if (2 * q + 1 < HH) part = fma(x[1], phi[2 * q + 1], part);
+            }
           } else {
-            const float* r16 = p.R16_32 + ((int64_t)ct * 4 + r) * HH;
+            const v4f* r16 = reinterpret_cast<const v4f*>(p.R16_32 + ((int64_t)ct * 4 + r) * (Q4 * 4));
 #pragma unroll
-            for (int t = 0; t < HH; ++t) part = fma((T)r16[t], phi[t], part);
+            for (int q = 0; q < Q4; ++q) {
+              const v4f x = r16[q];
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+                if (4 * q + i < HH) part = fma((T)x[i], phi[4 * q + i], part);
+            }
           }
           part += __shfl_xor(part, 16);
           part += __shfl_xor(part, 32);

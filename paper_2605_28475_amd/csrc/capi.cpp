@@ -281,6 +281,11 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   };
   for (int mode = 0; mode < 3; ++mode) h->slots[mode] = pick_slots(mode);
   const int H = h->H, HH = H * H, RT = h->RT, UU = (HH + 7) / 8;   // RT == 2: NK = 17
+  // FP32 tiles hold 4 steps t per lane ([NTm][Q4][64][4]) and FP64 tiles 2 ([NTm][Q2][64][2]),
+  // so that the kernels load them as vectors; the row-16 vectors are padded to 4 Q4 values
+  const int Q4 = (HH + 3) / 4, Q2 = (HH + 1) / 2, HHp = 4 * Q4;
+  auto idx32 = [&](int m, int t, int ln) { return (((size_t)m * Q4 + t / 4) * 64 + ln) * 4 + t % 4; };
+  auto idx64 = [&](int m, int t, int ln) { return (((size_t)m * Q2 + t / 2) * 64 + ln) * 2 + t % 2; };
   // A-operand value for lane group r at step t: the group's quadrant starts at k = 0
   // (lower half) or k = tile_upper_k (upper half); upper-half rows outside [H, NK), the
   // one shared with the lower half or the one past the end, have zero weight.
@@ -304,17 +309,16 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   // NK = 17: row k1 = 16 of every merged channel per lane group, for the VALU dot product
   std::vector<double> r16;
   if (RT == 2) {
-    r16.assign((size_t)NTm * 4 * HH, 0.0);
+    r16.assign((size_t)NTm * 4 * HHp, 0.0);
     for (int m = 0; m < NTm; ++m)
       for (int r = 0; r < 4; ++r)
-        for (int t = 0; t < HH; ++t) r16[((size_t)m * 4 + r) * HH + t] = Rval(m, 16, t, r);
+        for (int t = 0; t < HH; ++t) r16[((size_t)m * 4 + r) * HHp + t] = Rval(m, 16, t, r);
   }
   if (want64) {
-    std::vector<double> t64((size_t)NTm * HH * 64);
+    std::vector<double> t64((size_t)NTm * Q2 * 64 * 2, 0.0);
     for (int m = 0; m < NTm; ++m)
       for (int t = 0; t < HH; ++t)
-        for (int ln = 0; ln < 64; ++ln)
-          t64[((size_t)m * HH + t) * 64 + ln] = Rval(m, ln & 15, t, ln >> 4);
+        for (int ln = 0; ln < 64; ++ln) t64[idx64(m, t, ln)] = Rval(m, ln & 15, t, ln >> 4);
     if (!upload(h, h->d_Rt64, t64, s) || !upload(h, h->d_mg64, mg64, s)) return false;
     if (RT == 2 && !upload(h, h->d_R16_64, r16, s)) return false;
   }
@@ -323,26 +327,29 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     if (!upload(h, h->d_R16_32, r16f, s)) return false;
   }
   if (want32) {
-    std::vector<float> t32((size_t)NTm * HH * 64);
+    std::vector<float> t32((size_t)NTm * Q4 * 64 * 4, 0.0f);
     for (int m = 0; m < NTm; ++m)
       for (int t = 0; t < HH; ++t)
-        for (int ln = 0; ln < 64; ++ln)
-          t32[((size_t)m * HH + t) * 64 + ln] = (float)Rval(m, ln & 15, t, ln >> 4);
+        for (int ln = 0; ln < 64; ++ln) t32[idx32(m, t, ln)] = (float)Rval(m, ln & 15, t, ln >> 4);
     if (!upload(h, h->d_Rt32, t32, s)) return false;
   }
   if (wantD) {                // the antisymmetric tiles in the same layouts (FP64 and FP32)
     std::vector<double> d16;
     if (RT == 2) {
-      d16.assign((size_t)NTm * 4 * HH, 0.0);
+      d16.assign((size_t)NTm * 4 * HHp, 0.0);
       for (int m = 0; m < NTm; ++m)
         for (int r = 0; r < 4; ++r)
-          for (int t = 0; t < HH; ++t) d16[((size_t)m * 4 + r) * HH + t] = Tval(Dm, m, 16, t, r);
+          for (int t = 0; t < HH; ++t) d16[((size_t)m * 4 + r) * HHp + t] = Tval(Dm, m, 16, t, r);
     }
-    std::vector<double> t64((size_t)NTm * HH * 64);
+    std::vector<double> t64((size_t)NTm * Q2 * 64 * 2, 0.0);
+    std::vector<float> t32((size_t)NTm * Q4 * 64 * 4, 0.0f);
     for (int m = 0; m < NTm; ++m)
       for (int t = 0; t < HH; ++t)
-        for (int ln = 0; ln < 64; ++ln) t64[((size_t)m * HH + t) * 64 + ln] = Tval(Dm, m, ln & 15, t, ln >> 4);
-    std::vector<float> t32(t64.begin(), t64.end());
+        for (int ln = 0; ln < 64; ++ln) {
+          const double v = Tval(Dm, m, ln & 15, t, ln >> 4);
+          t64[idx64(m, t, ln)] = v;
+          t32[idx32(m, t, ln)] = (float)v;
+        }
     if ((want64 && !upload(h, h->d_Dt64, t64, s)) || (want32 && !upload(h, h->d_Dt32, t32, s))) return false;
     if (RT == 2) {
       std::vector<float> d16f(d16.begin(), d16.end());

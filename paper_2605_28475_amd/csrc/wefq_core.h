@@ -55,9 +55,9 @@ struct wefq_core {
   uint32_t* d_mq_pad = nullptr;        // the same with the padded pitch NK+1 (16-cell tiles)
   float* d_mg = nullptr;               // merged weights
   double* d_mg64 = nullptr;            // merged weights, FP64
-  float* d_Rt32 = nullptr;             // [NTm][H*H][64]  (rows k1 < 16)
-  double* d_Rt64 = nullptr;            // [NTm][H*H][64]
-  float* d_R16_32 = nullptr;           // NK = 17: row k1 = 16, [NTm][4][H*H]
+  float* d_Rt32 = nullptr;             // [NTm][ceil(H*H/4)][64][4]  (rows k1 < 16)
+  double* d_Rt64 = nullptr;            // [NTm][ceil(H*H/2)][64][2]
+  float* d_R16_32 = nullptr;           // NK = 17: row k1 = 16, [NTm][4][4 ceil(H*H/4)]
   double* d_R16_64 = nullptr;
   float* d_Dt32 = nullptr;             // antisymmetric partner tiles (bilinear form), layout of d_Rt32
   double* d_Dt64 = nullptr;
