@@ -88,7 +88,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   constexpr int NP = GQ / SLOTS > 0 ? GQ / SLOTS : 1;
   // The two-buffer coupling pipeline (below) where it was measured faster: FP32 at quadrants
   // of 6 to 8 and BF16x3 from 6 up, one input.  It costs 3H (pairs) more registers, which
-  // spill in FP64 and in FP32 at 9x9, and costs occupancy below 6x6.
+  // spill in FP64, cost occupancy below 6x6, and made FP32 at 9x9 slower (K = L = 16: 73.3
+  // against 62.6 ms).
   constexpr bool PIPE = !TWO && ((MODE == 0 && H >= 6 && H <= 8) || (MODE == 1 && H >= 6));
   // Without the pipeline, tiles of several output states per column group fetch each lane's
   // own routing rows through vector loads (VR) or each slot's rows through scalar loads.
