@@ -92,8 +92,8 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   // against 62.6 ms).
   constexpr bool PIPE = !TWO && ((MODE == 0 && H >= 6 && H <= 8) || (MODE == 1 && H >= 6));
   // Without the pipeline, tiles of several output states per column group fetch each lane's
-  // own routing rows through vector loads (VR) or each slot's rows through scalar loads.
-  constexpr bool VR = !TWO && SLOTS > 1;
+  // own routing rows through vector loads (VR), one input or two.
+  constexpr bool VR = SLOTS > 1;
   T* fs = reinterpret_cast<T*>(lds_raw);
   int& unit_ctr = *unit_ctr_p;
   T* Qo = static_cast<T*>(p.Q);
