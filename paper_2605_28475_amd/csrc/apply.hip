@@ -243,6 +243,7 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
   const int64_t ntiles = (B + TB - 1) / TB;
   p.nsplit = tile_splits(h, ntiles, p.nunits, h->split_per_cu[mode],
                          (int64_t)h->cu_count * h->resident_per_cu[mode]);
+  if (use_units2(h, mode, slots, p.nsplit, block)) { p.units = h->d_units2; p.nunits = h->nunits2; }
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   // a launch holds at most 2^32 - 1 threads: larger batches run as several launches of whole
   // tiles (each cell's result does not depend on its batch)

@@ -428,6 +428,12 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
     h->nunits8 = build_units(8, u8, c8);
     if (!upload(h, h->d_units8, u8, s)) return false;
   }
+  {
+    std::vector<int> u2;
+    double c2 = 0.0;
+    h->nunits2 = build_units(2, u2, c2);
+    if (!upload(h, h->d_units2, u2, s)) return false;
+  }
   if (!upload(h, h->d_units, uarr, s) || !upload(h, h->d_chan_begin, chan_begin, s) ||
       !upload(h, h->d_slice_off, slice_off, s) || !upload(h, h->d_sptr, sptr, s) ||
       !upload(h, h->d_spair, spair, s) ||

@@ -70,6 +70,8 @@ struct wefq_core {
   long alloc_count = 0;                // device allocations so far (failure-path test hook)
   int* d_units8 = nullptr;             // units of 8 output states (FP64 two-input tiles, H >= 7)
   int nunits8 = 0;
+  int* d_units2 = nullptr;             // units of 2 output states (short launches, see unit_list)
+  int nunits2 = 0;
   int GQ = 0;                          // q1 per unit
   double tile_cost = 0.0;              // estimated cost of one full 16-cell tile (scheduling only)
   int lds_limit = 0;                   // usable LDS bytes per workgroup
@@ -148,6 +150,21 @@ inline int tile_splits(const wefq_core* h, int64_t ntiles, int nunits, int per_c
     if (t < best_t) { best_t = t; best = n; }
   }
   return best;
+}
+
+// Units of 2 output states for a launch whose workgroups would hold fewer than 2 units of 4
+// per wave (one slot per column group, FP32 and BF16x3): more, shorter units even out the
+// waves' chains.  Measured on one MI355X against units of 4 (ms): K = L = 8, 4,096 cells, FP32
+// 0.315 -> 0.297 and BF16x3 0.265 -> 0.240; K = L = 12, 1,024 cells, FP32 0.917 -> 0.775.  At 2
+// or more units of 4 per wave they were equal or slower (K = L = 8 with 8,192 cells: 0.549 ->
+// 0.568 ms; K = L = 12 with 8,192: 4.92 -> 5.05 ms), and slower in FP64 (0.540 -> 0.555 ms at
+// K = L = 8, 4,096 cells), whose R tile is loaded per unit and channel.  Every output row
+// still belongs to one unit and one wave and is summed in the same order: the choice never
+// changes results.
+inline bool use_units2(const wefq_core* h, int mode, int slots, int nsplit, int block) {
+  if (!h->d_units2 || mode == 2 || slots != 1) return false;
+  const int64_t waves = (int64_t)nsplit * (block / 64);
+  return (int64_t)h->nunits < 2 * waves;
 }
 
 // Kernel mode of a precision: 0 FP32, 1 BF16X3, 2 FP64 (tiled); -1 otherwise.

@@ -122,10 +122,12 @@ def test_cell_result_independent_of_batch(prec):
         assert np.array_equal(alone[0], full[b])
 
 
-@pytest.mark.parametrize("K,prec", [(12, "fp32"), (12, "fp64"), (16, "fp32"), (16, "bf16x3")])
+@pytest.mark.parametrize("K,prec", [(12, "fp32"), (12, "fp64"), (16, "fp32"), (16, "bf16x3"), (8, "fp32"),
+                                    (8, "bf16x3")])
 def test_split_tiles_bitwise_equal(K, prec):
     """A batch large enough for one workgroup per cell tile and small batches whose tiles
-    are split over several workgroups give bitwise equal results per cell."""
+    are split over several workgroups give bitwise equal results per cell.  The small FP32
+    and BF16x3 batches also take the list of 2-state work units."""
     core = gpu_core("vhs", K, K, 0.5)
     slots, _ = core.tune_get(prec)
     B = 512 * (16 // slots)                       # >= 2 workgroups per CU: no split
