@@ -27,7 +27,8 @@ struct MfmaParams {
   const int* slice_off;    // [NTm]
   const int* sptr;         // slices + 1
   const int* spair;        // per slice: first single row; rows [sptr[s], spair[s]) are q2 pairs
-  const uint32_t* mq;      // q2*NKp | (q3*NKp) << 16: LDS row offsets of the two gathered states
+  const uint32_t* mq;      // [rows][2]: q2*NKp, q3*NKp, the LDS row offsets of the two gathered states
+                           // (swapped in the second row of a pair: a pair reads as u, a, b, u)
   const uint32_t* mq_pad;  // the same with the padded row pitch (16-cell tiles with a pad row)
   const float* mg;         // merged weights (FP32 / BF16X3)
   const double* mg64;      // merged weights (FP64)
@@ -91,9 +92,6 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   // spill in FP64, cost occupancy below 6x6, and made FP32 at 9x9 slower (K = L = 16: 73.3
   // against 62.6 ms).
   constexpr bool PIPE = !TWO && ((MODE == 0 && H >= 6 && H <= 8) || (MODE == 1 && H >= 6));
-  // Without the pipeline, tiles of several output states per column group fetch each lane's
-  // own routing rows through vector loads (VR), one input or two.
-  constexpr bool VR = SLOTS > 1;
   T* fs = reinterpret_cast<T*>(lds_raw);
   int& unit_ctr = *unit_ctr_p;
   T* Qo = static_cast<T*>(p.Q);
@@ -161,7 +159,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   // (the pipelined loops walk them with running pointers, one add per pointer and step)
   int vz;
   asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
-  const uint32_t* mqv = (pd ? p.mq_pad : p.mq) + vz;
+  const uint32_t* mqv = (pd ? p.mq_pad : p.mq) + vz;   // two words per row
   const T* mgv = (MODE == 2 ? reinterpret_cast<const T*>(p.mg64) : reinterpret_cast<const T*>(p.mg)) + vz;
   while (true) {
     int u = 0;
@@ -223,10 +221,14 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
         // two rows.  A single adds (g f_{k2,q2}) f_{k3,q3}.  With two inputs c, d (the
         // Jacobian-vector product) each product x (x) y becomes c_x (x) d_y + d_x (x) c_y.
         auto weight = [&](int e) -> T { return MODE == 2 ? (T)mg64[e] : (T)mg[e]; };
-        auto gather = [&](uint32_t qa, uint32_t qb, Rows<T, H, TWO>& x, bool pair) {
-          const T* pu = lane_u + (int)(qa & 0xffffu) * TB;
-          const T* pa = lane_w + (int)(qa >> 16) * TB;
-          const T* pb = lane_w + (int)(qb >> 16) * TB;
+        // A step's routing: the LDS row offsets of the q2 row (u) and of the q3 rows (a, and b
+        // for a pair), each a word of its own, so that an address is one shift-and-add from
+        // the lane's base; and the weights.
+        struct Route { uint32_t u, a, b; T ga, gb; };
+        auto gather = [&](const Route& rt, Rows<T, H, TWO>& x, bool pair) {
+          const T* pu = lane_u + (int)rt.u * TB;
+          const T* pa = lane_w + (int)rt.a * TB;
+          const T* pb = lane_w + (int)rt.b * TB;
 #pragma unroll
           for (int a = 0; a < H; ++a) {
             x.u[a] = pu[a * TB];
@@ -274,53 +276,52 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
         // and weights) come through vector loads two rows ahead: a scalar load there would
         // share the LDS counter, and every wait for it would also wait for all gathers in
         // flight.  The arrays carry 8 entries of tail slack (row offset 0, weight 0).
-        // rows: number of rows (or pairs) of this lane's slice; fetch(i, qa, qb, ga, gb):
-        // routing of row i of it (zero weight past its end); pair: two rows per step.
-        auto pipeline = [&](int rows, int maxrows, auto fetch, bool pair) {
+        // maxrows: steps (rows or pairs) of the longest slice among the wave's lanes; fetch(i, rt):
+        // routing of step i of this lane's slice (zero weight past its end); pair: two rows per step.
+        auto pipeline = [&](int maxrows, auto fetch, bool pair) {
           if (maxrows <= 0) return;
-          uint32_t qa0, qb0, qa1, qb1;
-          T ga0, gb0, ga1, gb1;
-          fetch(0, qa0, qb0, ga0, gb0);
-          fetch(1, qa1, qb1, ga1, gb1);
+          Route r0, r1;
+          fetch(0, r0);
+          fetch(1, r1);
           Rows<T, H, TWO> A, B;
-          gather(qa0, qb0, A, pair);
+          gather(r0, A, pair);
           int i = 0;
           for (; i + 1 < maxrows; i += 2) {
-            uint32_t qa2, qb2, qa3, qb3;
-            T ga2, gb2, ga3, gb3;
-            fetch(i + 2, qa2, qb2, ga2, gb2);
-            gather(qa1, qb1, B, pair);
+            Route r2, r3;
+            fetch(i + 2, r2);
+            gather(r1, B, pair);
             __builtin_amdgcn_sched_barrier(0);
-            if (pair) pair_acc(ga0, gb0, A); else single_acc(ga0, A);
+            if (pair) pair_acc(r0.ga, r0.gb, A); else single_acc(r0.ga, A);
             __builtin_amdgcn_sched_barrier(0);
-            fetch(i + 3, qa3, qb3, ga3, gb3);
-            gather(qa2, qb2, A, pair);
+            fetch(i + 3, r3);
+            gather(r2, A, pair);
             __builtin_amdgcn_sched_barrier(0);
-            if (pair) pair_acc(ga1, gb1, B); else single_acc(ga1, B);
+            if (pair) pair_acc(r1.ga, r1.gb, B); else single_acc(r1.ga, B);
             __builtin_amdgcn_sched_barrier(0);
-            ga0 = ga2; gb0 = gb2; ga1 = ga3; gb1 = gb3; qa1 = qa3; qb1 = qb3;
+            r0 = r2;
+            r1 = r3;
           }
           if (i < maxrows) {
-            if (pair) pair_acc(ga0, gb0, A); else single_acc(ga0, A);
+            if (pair) pair_acc(r0.ga, r0.gb, A); else single_acc(r0.ga, A);
           }
-          (void)rows;
         };
         if constexpr (PIPE && SLOTS == 1) {     // the slice is shared by the whole wave
           const int s = soff + units[ub + 2 + gi];
           const int e0 = sptr[s], e1 = sptr[s + 1], ep = spair[s];
           const int np_ = (ep - e0) >> 1, ns_ = e1 - ep;
-          // rows are fetched in order, up to two past the end (within the table's slack)
-          const uint32_t* pq = mqv + e0;
+          // rows are fetched in order, up to two steps past the end (within the table's slack);
+          // a pair is rows (q2, q3a), (q2, q3b), stored as words u, a, b, u
+          const uint32_t* pq = mqv + 2 * e0;
           const T* pw = mgv + e0;
-          pipeline(np_, np_, [&](int, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
-            qa = pq[0]; qb = pq[1]; ga = pw[0]; gb = pw[1];
-            pq += 2; pw += 2;
+          pipeline(np_, [&](int, Route& rt) {
+            rt.u = pq[0]; rt.a = pq[1]; rt.b = pq[2]; rt.ga = pw[0]; rt.gb = pw[1];
+            pq += 4; pw += 2;
           }, true);
-          pq = mqv + ep;
+          pq = mqv + 2 * ep;
           pw = mgv + ep;
-          pipeline(ns_, ns_, [&](int, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
-            qa = pq[0]; qb = 0u; ga = pw[0]; gb = T(0);
-            pq += 1; pw += 1;
+          pipeline(ns_, [&](int, Route& rt) {
+            rt.u = pq[0]; rt.a = pq[1]; rt.b = 0u; rt.ga = pw[0]; rt.gb = T(0);
+            pq += 2; pw += 1;
           }, false);
         } else if constexpr (PIPE) {
           // Lanes of different output states walk different slices: every lane fetches its
@@ -348,24 +349,26 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
             if (slot == sl) { my0 = se0[sl]; myp = sep[sl]; my1 = se1[sl]; }
           const int my_np = (myp - my0) >> 1, my_ns = my1 - myp;
           // each lane's pointers stop at the end of its slot's rows, where they still read
-          // valid table entries (the slot's singles, or the slack); those reads are masked
-          const uint32_t* pq = mqv + my0;
+          // valid table entries (the slot's singles, the next slice, or the slack); those
+          // reads are masked
+          const uint32_t* pq = mqv + 2 * my0;
           const T* pw = mgv + my0;
-          pipeline(my_np, maxp, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+          pipeline(maxp, [&](int i, Route& rt) {
             const bool in = i < my_np;
-            const uint32_t xa = pq[0], xb = pq[1];
+            const uint32_t xu = pq[0], xa = pq[1], xb = pq[2];
             const T ya = pw[0], yb = pw[1];
-            qa = in ? xa : 0u; qb = in ? xb : 0u; ga = in ? ya : T(0); gb = in ? yb : T(0);
-            pq += in ? 2 : 0; pw += in ? 2 : 0;
+            rt.u = in ? xu : 0u; rt.a = in ? xa : 0u; rt.b = in ? xb : 0u;
+            rt.ga = in ? ya : T(0); rt.gb = in ? yb : T(0);
+            pq += in ? 4 : 0; pw += in ? 2 : 0;
           }, true);
-          pq = mqv + myp;
+          pq = mqv + 2 * myp;
           pw = mgv + myp;
-          pipeline(my_ns, maxs, [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
+          pipeline(maxs, [&](int i, Route& rt) {
             const bool in = i < my_ns;
-            const uint32_t xa = pq[0];
+            const uint32_t xu = pq[0], xa = pq[1];
             const T ya = pw[0];
-            qa = in ? xa : 0u; qb = 0u; ga = in ? ya : T(0); gb = T(0);
-            pq += in ? 1 : 0; pw += in ? 1 : 0;
+            rt.u = in ? xu : 0u; rt.a = in ? xa : 0u; rt.b = 0u; rt.ga = in ? ya : T(0); rt.gb = T(0);
+            pq += in ? 2 : 0; pw += in ? 1 : 0;
           }, false);
         } else if constexpr (SLOTS == 1) {
           // Without the two row buffers (where registers do not allow them): one row's
@@ -375,38 +378,43 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
           // software pipeline: the gathers of the next row (pair) are in flight
           // while the outer product of the current one accumulates (the arrays
           // carry tail slack, whose row offsets point at LDS row 0)
+          auto pair_route = [&](int e) {
+            return Route{mq[2 * e], mq[2 * e + 1], mq[2 * e + 2], weight(e), weight(e + 1)};
+          };
+          auto single_route = [&](int e) { return Route{mq[2 * e], mq[2 * e + 1], 0u, weight(e), T(0)}; };
           if (e0 < ep) {
-            T ga = weight(e0), gb = weight(e0 + 1);
+            Route rc = pair_route(e0);
             Rows<T, H, TWO> cur;
-            gather(mq[e0], mq[e0 + 1], cur, true);
+            gather(rc, cur, true);
             for (int e = e0; e < ep; e += 2) {
-              const T gna = weight(e + 2), gnb = weight(e + 3);
+              const Route rn = pair_route(e + 2);
               Rows<T, H, TWO> nxt;
-              gather(mq[e + 2], mq[e + 3], nxt, true);
-              pair_acc(ga, gb, cur);
+              gather(rn, nxt, true);
+              pair_acc(rc.ga, rc.gb, cur);
               cur = nxt;
-              ga = gna;
-              gb = gnb;
+              rc = rn;
             }
           }
           if (ep < e1) {
-            T gg = weight(ep);
+            Route rc = single_route(ep);
             Rows<T, H, TWO> cur;
-            gather(mq[ep], 0u, cur, false);
+            gather(rc, cur, false);
             for (int e = ep; e < e1; ++e) {
-              const T gn = weight(e + 1);
+              const Route rn = single_route(e + 1);
               Rows<T, H, TWO> nxt;
-              gather(mq[e + 1], 0u, nxt, false);
-              single_acc(gg, cur);
+              gather(rn, nxt, false);
+              single_acc(rc.ga, cur);
               cur = nxt;
-              gg = gn;
+              rc = rn;
             }
           }
         } else {
-          // Lanes of different output states walk different slices.  Each slot's row
-          // range is wave-uniform, so its rows come through scalar loads and every lane
-          // keeps its own slot's row; the loops run to the longest slot, and rows past a
-          // slot's end carry weight zero and row offset 0.
+          // Lanes of different output states walk different slices: every lane fetches its
+          // own slot's rows through vector loads, walking running pointers that stop at the
+          // end of the slot's rows (where they still read valid entries: the slot's singles,
+          // the next slice, or the table's slack) and masking past it; the loops run to the
+          // longest slot, and rows past a slot's end carry weight zero and row offset 0 (all
+          // such lanes then read the same LDS row: a broadcast, not a bank conflict).
           int se0[SLOTS], sep[SLOTS], se1[SLOTS];
           int maxp = 0, maxs = 0;
 #pragma unroll
@@ -423,94 +431,58 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
             maxp = maxp > np_s ? maxp : np_s;
             maxs = maxs > ns_s ? maxs : ns_s;
           }
-          // VR: every lane fetches its own slot's rows through vector loads, walking
-          // running pointers that stop at the end of the slot's rows (where they still read
-          // valid entries: the slot's singles, or the table's slack) and masking past it;
-          // otherwise each slot's rows come through scalar loads and lanes select theirs
           int my0 = 0, myp = 0, my1 = 0;
 #pragma unroll
           for (int sl = 0; sl < SLOTS; ++sl)
             if (slot == sl) { my0 = se0[sl]; myp = sep[sl]; my1 = se1[sl]; }
           const int my_np = (myp - my0) >> 1, my_ns = my1 - myp;
-          const uint32_t* pqp = mqv + my0;
+          const uint32_t* pqp = mqv + 2 * my0;
           const T* pwp = mgv + my0;
-          const uint32_t* pqs = mqv + myp;
+          const uint32_t* pqs = mqv + 2 * myp;
           const T* pws = mgv + myp;
-          auto fetch_pair = [&](int i, uint32_t& qa, uint32_t& qb, T& ga, T& gb) {
-            if constexpr (VR) {
-              const bool in = i < my_np;
-              const uint32_t xa = pqp[0], xb = pqp[1];
-              const T ya = pwp[0], yb = pwp[1];
-              qa = in ? xa : 0u; qb = in ? xb : 0u; ga = in ? ya : T(0); gb = in ? yb : T(0);
-              pqp += in ? 2 : 0; pwp += in ? 2 : 0;
-              return;
-            }
-            qa = qb = 0u;
-            ga = gb = T(0);
-#pragma unroll
-            for (int sl = 0; sl < SLOTS; ++sl) {
-              if (i < ((sep[sl] - se0[sl]) >> 1)) {
-                const int e = se0[sl] + 2 * i;
-                const uint32_t xa = mq[e], xb = mq[e + 1];
-                const T ya = weight(e), yb = weight(e + 1);
-                if (slot == sl) { qa = xa; qb = xb; ga = ya; gb = yb; }
-              }
-            }
+          auto fetch_pair = [&](int i, Route& rt) {
+            const bool in = i < my_np;
+            const uint32_t xu = pqp[0], xa = pqp[1], xb = pqp[2];
+            const T ya = pwp[0], yb = pwp[1];
+            rt.u = in ? xu : 0u; rt.a = in ? xa : 0u; rt.b = in ? xb : 0u;
+            rt.ga = in ? ya : T(0); rt.gb = in ? yb : T(0);
+            pqp += in ? 4 : 0; pwp += in ? 2 : 0;
           };
-          auto fetch_single = [&](int i, uint32_t& qq, T& gg) {
-            if constexpr (VR) {
-              const bool in = i < my_ns;
-              const uint32_t x = pqs[0];
-              const T y = pws[0];
-              qq = in ? x : 0u; gg = in ? y : T(0);
-              pqs += in ? 1 : 0; pws += in ? 1 : 0;
-              return;
-            }
-            qq = 0u;
-            gg = T(0);
-#pragma unroll
-            for (int sl = 0; sl < SLOTS; ++sl) {
-              if (i < se1[sl] - sep[sl]) {
-                const int e = sep[sl] + i;
-                const uint32_t x = mq[e];
-                const T y = weight(e);
-                if (slot == sl) { qq = x; gg = y; }
-              }
-            }
+          auto fetch_single = [&](int i, Route& rt) {
+            const bool in = i < my_ns;
+            const uint32_t xu = pqs[0], xa = pqs[1];
+            const T y = pws[0];
+            rt.u = in ? xu : 0u; rt.a = in ? xa : 0u; rt.b = 0u; rt.ga = in ? y : T(0); rt.gb = T(0);
+            pqs += in ? 2 : 0; pws += in ? 1 : 0;
           };
           if (maxp > 0) {
-            uint32_t qa, qb;
-            T ga, gb;
+            Route rc;
             Rows<T, H, TWO> cur;
-            fetch_pair(0, qa, qb, ga, gb);
-            gather(qa, qb, cur, true);
+            fetch_pair(0, rc);
+            gather(rc, cur, true);
             for (int i = 0; i < maxp; ++i) {
-              uint32_t qna, qnb;
-              T gna, gnb;
+              Route rn;
               Rows<T, H, TWO> nxt;
-              fetch_pair(i + 1, qna, qnb, gna, gnb);
-              gather(qna, qnb, nxt, true);
-              pair_acc(ga, gb, cur);
+              fetch_pair(i + 1, rn);
+              gather(rn, nxt, true);
+              pair_acc(rc.ga, rc.gb, cur);
               cur = nxt;
-              ga = gna;
-              gb = gnb;
+              rc = rn;
             }
           }
           if (maxs > 0) {
-            uint32_t qq;
-            T gg;
+            Route rc;
             Rows<T, H, TWO> cur;
-            fetch_single(0, qq, gg);
-            gather(qq, 0u, cur, false);
+            fetch_single(0, rc);
+            gather(rc, cur, false);
             for (int i = 0; i < maxs; ++i) {
-              uint32_t qn;
-              T gn;
+              Route rn;
               Rows<T, H, TWO> nxt;
-              fetch_single(i + 1, qn, gn);
-              gather(qn, 0u, nxt, false);
-              single_acc(gg, cur);
+              fetch_single(i + 1, rn);
+              gather(rn, nxt, false);
+              single_acc(rc.ga, cur);
               cur = nxt;
-              gg = gn;
+              rc = rn;
             }
           }
         }

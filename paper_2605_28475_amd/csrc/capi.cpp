@@ -238,18 +238,24 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   for (int pad = 0; pad < 8; ++pad) { mq.push_back(0u); mg.push_back(0.0f); mg64.push_back(0.0); }  // tail slack
   h->NGm = ngm;
   h->NSm = nsm;
-  // row offsets for 16-cell tiles with a pad row per q block (pitch NK+1)
-  std::vector<uint32_t> mq_pad;
-  {
-    const int Hh = (NK + 1) / 2;
-    if (tile_pad_rows(NK, Hh, 16)) {
-      mq_pad.resize(mq.size());
-      for (size_t i = 0; i < mq.size(); ++i) {
-        uint32_t q2 = (mq[i] & 0xffffu) / NK, q3 = (mq[i] >> 16) / NK;
-        mq_pad[i] = (q2 * (NK + 1)) | ((q3 * (NK + 1)) << 16);
-      }
+  // The device tables hold each row's two LDS row offsets as words of their own (q2*pitch,
+  // q3*pitch), so that the kernel forms an address with one shift-and-add; the pitch is NK,
+  // and NK+1 for 16-cell tiles with a pad row per q block.  The second row of a pair stores
+  // its two words swapped (q3b first), so that a pair's three distinct offsets u = q2, a =
+  // q3a, b = q3b are its first three words and come in one load.
+  auto unpack_rows = [&](uint32_t pitch) {
+    std::vector<uint32_t> o(2 * mq.size());
+    for (size_t i = 0; i < mq.size(); ++i) {
+      o[2 * i] = (mq[i] & 0xffffu) / NK * pitch;
+      o[2 * i + 1] = (mq[i] >> 16) / NK * pitch;
     }
-  }
+    for (size_t sl = 0; sl + 1 < sptr.size(); ++sl)
+      for (int e = sptr[sl]; e + 1 < spair[sl]; e += 2) std::swap(o[2 * (e + 1)], o[2 * (e + 1) + 1]);
+    return o;
+  };
+  const std::vector<uint32_t> mq_rows = unpack_rows((uint32_t)NK);
+  std::vector<uint32_t> mq_pad;
+  if (tile_pad_rows(NK, (NK + 1) / 2, 16)) mq_pad = unpack_rows((uint32_t)(NK + 1));
   // MFMA geometry
   h->H = (NK + 1) / 2;
   h->RT = NK > 16 ? 2 : 1;
@@ -437,7 +443,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   if (!upload(h, h->d_units, uarr, s) || !upload(h, h->d_chan_begin, chan_begin, s) ||
       !upload(h, h->d_slice_off, slice_off, s) || !upload(h, h->d_sptr, sptr, s) ||
       !upload(h, h->d_spair, spair, s) ||
-      !upload(h, h->d_mq, mq, s) || !upload(h, h->d_mg, mg, s))
+      !upload(h, h->d_mq, mq_rows, s) || !upload(h, h->d_mg, mg, s))
     return false;
   if (mq_pad.empty()) h->d_mq_pad = h->d_mq;
   else if (!upload(h, h->d_mq_pad, mq_pad, s)) return false;

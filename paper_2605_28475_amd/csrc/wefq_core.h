@@ -51,7 +51,7 @@ struct wefq_core {
   int* d_slice_off = nullptr;          // NTm: first slice of the merged channel
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
   int* d_spair = nullptr;              // per slice: first single row (rows before it come in q2 pairs)
-  uint32_t* d_mq = nullptr;            // merged entries: q2*NK | (q3*NK) << 16
+  uint32_t* d_mq = nullptr;            // merged entries, two words each: q2*NK, q3*NK
   uint32_t* d_mq_pad = nullptr;        // the same with the padded pitch NK+1 (16-cell tiles)
   float* d_mg = nullptr;               // merged weights
   double* d_mg64 = nullptr;            // merged weights, FP64
