@@ -243,11 +243,13 @@ const char* wefq_last_error(void);
 
 /* Tile shape used by wefq_apply_Q for one precision of a core: slots = output
  * states sharing the 16 MFMA columns (1, 2 or 4; the cell tile is 16/slots cells
- * and must fit in LDS), block = threads per workgroup (256 or 512).  Results are
- * bitwise independent of the shape.  The default, set by wefq_build_core, is the
- * largest tile that fits in LDS with a kernel that spills at most 128 bytes of
- * registers per lane, at 512 threads (256 when a tile holds fewer than 16 work units of up
- * to 4 output states each); the autotuner may replace it.  Each precision keeps its own shape.
+ * and must fit in LDS), block = threads per workgroup (256, 512 or 768; 768 runs a kernel
+ * instance built for 12 waves, with fewer registers per lane).  Results are bitwise
+ * independent of the shape.  The default, set by wefq_build_core, is the largest tile that
+ * fits in LDS with a kernel that spills at most 128 bytes of registers per lane, at 512
+ * threads; 256 when a tile holds fewer than 16 work units of up to 4 output states each, and
+ * 768 when the 12-wave instance spills at most 64 bytes and keeps more waves resident per
+ * compute unit; the autotuner may replace it.  Each precision keeps its own shape.
  * Setting a shape also re-derives how small batches split their tiles over workgroups
  * (a residency query of the kernel on the core's device, which the call makes current).
  * EINVAL for an unknown precision, slots or block; EUNSUPPORTED when the tile does not

@@ -106,16 +106,17 @@ hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int
   return hipSuccess;
 }
 
-template <int H, int SLOTS, int RT, int MODE>
-__global__ __launch_bounds__(512) void apply_mfma_kernel(MfmaParams p) {
+// WAVES = 8 or 12 waves per workgroup (launches of up to 512 or 768 threads)
+template <int H, int SLOTS, int RT, int MODE, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void apply_mfma_kernel(MfmaParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int unit_ctr;
-  mfma_tile<H, SLOTS, RT, MODE>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw, &unit_ctr);
+  mfma_tile<H, SLOTS, RT, MODE, false, false, WAVES>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw, &unit_ctr);
 }
 
 template <int H, int SLOTS, int RT, int MODE>
 static hipError_t launch_mfma_t(const MfmaParams& p, int64_t ntiles, int block, size_t lds, hipStream_t s) {
-  auto k = apply_mfma_kernel<H, SLOTS, RT, MODE>;
+  auto k = block > 512 ? apply_mfma_kernel<H, SLOTS, RT, MODE, 12> : apply_mfma_kernel<H, SLOTS, RT, MODE, 8>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3((unsigned)ntiles, (unsigned)p.nsplit), dim3(block), lds, s, p);
@@ -123,66 +124,67 @@ static hipError_t launch_mfma_t(const MfmaParams& p, int64_t ntiles, int block, 
 }
 
 template <int H, int SLOTS, int RT, int MODE>
-static const void* kernel_t() {
-  return (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE>;
+static const void* kernel_t(bool wide) {
+  return wide ? (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE, 12> : (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE, 8>;
 }
 
-// One instance per (H, slots, RT, mode), chosen at run time; the launch dispatch below and
-// the attribute queries (spills, residency) see the same kernels.
+// One instance per (H, slots, RT, mode, waves), chosen at run time; the launch dispatch below
+// and the attribute queries (spills, residency) see the same kernels.
 template <int H, int RT, int MODE>
-static const void* kernel_s(int slots) {
+static const void* kernel_s(int slots, bool wide) {
   switch (slots) {
-    case 1: return kernel_t<H, 1, RT, MODE>();
-    case 2: return kernel_t<H, 2, RT, MODE>();
-    case 4: return kernel_t<H, 4, RT, MODE>();
+    case 1: return kernel_t<H, 1, RT, MODE>(wide);
+    case 2: return kernel_t<H, 2, RT, MODE>(wide);
+    case 4: return kernel_t<H, 4, RT, MODE>(wide);
     default: return nullptr;
   }
 }
 
 template <int H>
-static const void* kernel_h(int mode, int slots, int rt) {
+static const void* kernel_h(int mode, int slots, int rt, bool wide) {
   if (rt == 2) {
     if constexpr (H >= 8) {
       switch (mode) {
-        case 0: return kernel_s<H, 2, 0>(slots);
-        case 1: return kernel_s<H, 2, 1>(slots);
-        case 2: return kernel_s<H, 2, 2>(slots);
+        case 0: return kernel_s<H, 2, 0>(slots, wide);
+        case 1: return kernel_s<H, 2, 1>(slots, wide);
+        case 2: return kernel_s<H, 2, 2>(slots, wide);
       }
     }
     return nullptr;
   }
   switch (mode) {
-    case 0: return kernel_s<H, 1, 0>(slots);
-    case 1: return kernel_s<H, 1, 1>(slots);
-    case 2: return kernel_s<H, 1, 2>(slots);
+    case 0: return kernel_s<H, 1, 0>(slots, wide);
+    case 1: return kernel_s<H, 1, 1>(slots, wide);
+    case 2: return kernel_s<H, 1, 2>(slots, wide);
   }
   return nullptr;
 }
 
-static const void* mfma_kernel(const wefq_core* h, int mode, int slots) {
+static const void* mfma_kernel(const wefq_core* h, int mode, int slots, int block) {
+  const bool wide = block > 512;
   switch (h->H) {
-    case 1: return kernel_h<1>(mode, slots, h->RT);
-    case 2: return kernel_h<2>(mode, slots, h->RT);
-    case 3: return kernel_h<3>(mode, slots, h->RT);
-    case 4: return kernel_h<4>(mode, slots, h->RT);
-    case 5: return kernel_h<5>(mode, slots, h->RT);
-    case 6: return kernel_h<6>(mode, slots, h->RT);
-    case 7: return kernel_h<7>(mode, slots, h->RT);
-    case 8: return kernel_h<8>(mode, slots, h->RT);
-    case 9: return kernel_h<9>(mode, slots, h->RT);
+    case 1: return kernel_h<1>(mode, slots, h->RT, wide);
+    case 2: return kernel_h<2>(mode, slots, h->RT, wide);
+    case 3: return kernel_h<3>(mode, slots, h->RT, wide);
+    case 4: return kernel_h<4>(mode, slots, h->RT, wide);
+    case 5: return kernel_h<5>(mode, slots, h->RT, wide);
+    case 6: return kernel_h<6>(mode, slots, h->RT, wide);
+    case 7: return kernel_h<7>(mode, slots, h->RT, wide);
+    case 8: return kernel_h<8>(mode, slots, h->RT, wide);
+    case 9: return kernel_h<9>(mode, slots, h->RT, wide);
     default: return nullptr;
   }
 }
 
-int mfma_spill_bytes(const wefq_core* h, int mode, int slots) {
-  const void* k = mfma_kernel(h, mode, slots);
+int mfma_spill_bytes(const wefq_core* h, int mode, int slots, int block) {
+  const void* k = mfma_kernel(h, mode, slots, block);
   hipFuncAttributes a;
   if (!k || hipFuncGetAttributes(&a, k) != hipSuccess) return -1;
   return (int)a.localSizeBytes;
 }
 
 int mfma_blocks_per_cu(const wefq_core* h, int mode, int slots, int block) {
-  const void* k = mfma_kernel(h, mode, slots);
+  const void* k = mfma_kernel(h, mode, slots, block);
   if (!k) return 0;
   const size_t lds = tile_lds_bytes(h, slots, mode == 2 ? 8 : 4);
   int n = 0;

@@ -73,10 +73,12 @@ __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
 // One cell tile: stage f, then process the (l1, q1-group) work units split, split + nsplit, ...
 // (all of them when nsplit = 1).  Each output row belongs to one unit, so splitting a tile
 // over several workgroups changes neither the work per row nor its order.
+// WAVES: waves per workgroup the instance is built for, 8 or 12 (three per SIMD, which leaves
+// each lane 168 registers: the 12-wave instances hoist the R tile only up to 6x6 quadrants).
 // TWO: two inputs f, g; the coupling is symmetric, sum w (f_x (x) g_y + g_x (x) f_y), or with
 // ANTI antisymmetric, sum w (f_x (x) g_y - g_x (x) f_y), contracted with the tiles the caller
 // passes as the A operand, and the result combined as out = (out + result) / 2.
-template <int H, int SLOTS, int RT, int MODE, bool TWO = false, bool ANTI = false>
+template <int H, int SLOTS, int RT, int MODE, bool TWO = false, bool ANTI = false, int WAVES = 8>
 __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int split, unsigned char* lds_raw,
                                           int* unit_ctr_p) {
   typedef typename ModeTraits<MODE>::T T;
@@ -182,7 +184,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
       // The channel's R tile is the MFMA A operand for every q1 of the unit.  When
       // registers allow, it is loaded once per channel ahead of the first coupling,
       // so its latency hides behind the VALU work; otherwise it streams in batches.
-      constexpr bool HOIST = MODE == 2 ? (H <= 4) : (H <= 7);
+      constexpr bool HOIST = MODE == 2 ? (H <= 4) : (H <= (WAVES > 8 ? 6 : 7));
       float a32[HOIST && MODE == 0 ? Q4 * 4 : 1];
       double a64[HOIST && MODE == 2 ? Q2 * 2 : 1];
       v8bf ahi[HOIST && MODE == 1 ? U : 1], alo[HOIST && MODE == 1 ? U : 1];

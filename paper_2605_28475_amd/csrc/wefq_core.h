@@ -216,9 +216,10 @@ hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int
                              int64_t ldf, int64_t ldq, hipStream_t s);
 hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, void* Q,
                              int64_t B, int64_t ldf, int64_t ldq, hipStream_t s);
-// Private (scratch) bytes per lane of the MFMA kernel instance of a tile shape:
-// nonzero when it spills registers.  Returns -1 for a shape with no instance.
-int mfma_spill_bytes(const wefq_core* h, int mode, int slots);
+// Private (scratch) bytes per lane of the MFMA kernel instance of a tile shape and block size
+// (the 12-wave instance above 512 threads): nonzero when it spills registers.  Returns -1 for
+// a shape with no instance.
+int mfma_spill_bytes(const wefq_core* h, int mode, int slots, int block);
 // Workgroups of the apply kernel for (mode, slots) resident per compute unit at the given
 // block size with its LDS tile; 0 when the query fails.
 int mfma_blocks_per_cu(const wefq_core* h, int mode, int slots, int block);

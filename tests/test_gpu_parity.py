@@ -122,6 +122,31 @@ def test_cell_result_independent_of_batch(prec):
         assert np.array_equal(alone[0], full[b])
 
 
+@pytest.mark.parametrize("K", [3, 5, 8, 10, 12, 14, 16])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_wide_workgroups_bitwise_equal(K, prec):
+    """The 12-wave kernel instances (768 threads; the R tile is not hoisted from 7x7
+    quadrants up) give bitwise the results of the 8-wave instances, at the default tile shape
+    and at one other."""
+    core = gpu_core("hs", K, K, 1.0)
+    old = core.tune_get(prec)
+    B = 40 if K >= 14 else 100
+    c = synth.perturbed_maxwellian(K, K, B, seed=synth.BASE_SEED + 900 + K)
+    say(f"[wide] K={K} {prec} default {old}")
+    try:
+        for slots in (old[0], 4 if old[0] != 4 else 2):
+            try:
+                core.tune_set(prec, slots, 512)
+            except wefq.WefqError:
+                continue                                  # tile does not fit in LDS
+            narrow = run(core, c, prec)
+            core.tune_set(prec, slots, 768)
+            wide = run(core, c, prec)
+            assert np.array_equal(narrow, wide), slots
+    finally:
+        core.tune_set(prec, *old)
+
+
 @pytest.mark.parametrize("K,prec", [(12, "fp32"), (12, "fp64"), (16, "fp32"), (16, "bf16x3"), (8, "fp32"),
                                     (8, "bf16x3")])
 def test_split_tiles_bitwise_equal(K, prec):
