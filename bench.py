@@ -264,6 +264,8 @@ def main():
     ap.add_argument("--tick-ms", type=float, default=16.0, help="serve: work per scheduling tick, in ms")
     ap.add_argument("--serve-depth", type=int, default=2, help="serve: launches in flight")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=None, help="serve: arrival rates (req/s)")
+    ap.add_argument("--serve-tflops", type=float, default=None, help="serve: rate that sizes a tick (TFLOP/s)")
+    ap.add_argument("--serve-block", type=int, default=None, help="serve: threads per workgroup (256 or 512)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of f (known byte count) for counter scaling")
     args = ap.parse_args()
@@ -703,7 +705,10 @@ def bench_uneven(args, torch, wefq, synth):
             flop += core.info["flop_alg_per_cell"] * B
     log("[uneven] autotuning whole plans")
     slots, blk, tried = autotune.tune_plan(segs, "fp32")
-    default_ms = tried["block=512 slots=" + ",".join("0" for _ in segs)]
+    # the tuner's starting point: every core's default shape at its first block size
+    zeros = "slots=" + ",".join("0" for _ in segs)
+    default_key = next(k for k in tried if k.endswith(zeros))
+    default_ms = tried[default_key]
     segs_used = [(c, f, q, s if s else c.tune_get("fp32")[0]) for (c, f, q), s in zip(segs, slots)]
     plan = wefq.Plan(segs_used, precision="fp32", block=blk)
     shape_name = "autotuned on whole plans"
@@ -730,6 +735,7 @@ def bench_uneven(args, torch, wefq, synth):
                         "frac": flop / t / 1e12 / PEAK["fp32"], "traffic": None},
            "graph_ms": float(np.mean(ms)), "direct_ms": float(np.mean(ms_direct)),
            "separate_launches_ms": float(np.mean(ms_sep)), "default_shapes_ms": default_ms,
+           "default_shapes": default_key,
            "autotune_candidates_ms": tried}
     print(json.dumps(out), flush=True)
 

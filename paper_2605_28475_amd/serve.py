@@ -94,7 +94,7 @@ class Server:
     FLOPs.  streams is accepted for compatibility: ticks run on one stream."""
 
     def __init__(self, torch, cores, pools, budget_bytes, streams=1, max_inflight=2, device=0, tick_ms=16.0,
-                 rate_tflops=140.0, precision="fp32", pack_tiles=2):
+                 rate_tflops=140.0, precision="fp32", pack_tiles=2, block=None):
         import paper_2605_28475_amd as wefq
         self.torch = torch
         self.cores = cores                 # list of Core
@@ -103,7 +103,9 @@ class Server:
         self.arena = Arena(torch, budget_bytes // 4, self.dev)
         self.stream = torch.cuda.Stream(device=self.dev)
         self.depth = max(1, int(max_inflight))
-        self.runner = wefq.Runner(device, precision)
+        # threads per workgroup of the persistent kernel (256 or 512)
+        self.block = int(block) if block else 512
+        self.runner = wefq.Runner(device, precision, block=self.block)
         self.tile = [16 // c.tune_get(precision)[0] for c in cores]
         self.fpc = [float(c.info["flop_alg_per_cell"]) for c in cores]
         self.tick_flop = tick_ms * 1e-3 * rate_tflops * 1e12
@@ -250,7 +252,7 @@ class Server:
 def make_server(torch, sizes=(8, 12, 16), model="hs", pool_cells=4096, budget_gb=8.0, streams=1, device=0,
                 precision="fp32", **server_args):
     """Resident hard-sphere cores K = L in sizes and seeded resident cell pools; server_args go
-    to Server (tick_ms, max_inflight, rate_tflops, pack_tiles)."""
+    to Server (tick_ms, max_inflight, rate_tflops, pack_tiles, block)."""
     import paper_2605_28475_amd as wefq
     dev = torch.device("cuda", device)
     cores, pools = [], []
@@ -270,7 +272,13 @@ def bench(args):
     cfg = synth.WORKLOADS["serving"]
     tick_ms = float(getattr(args, "tick_ms", 16.0))
     depth = int(getattr(args, "serve_depth", 2))
-    srv = make_server(torch, sizes=cfg["sizes"], pool_cells=cfg["max_cells"], tick_ms=tick_ms, max_inflight=depth)
+    extra = {}
+    if getattr(args, "serve_tflops", None):
+        extra["rate_tflops"] = float(args.serve_tflops)
+    if getattr(args, "serve_block", None):
+        extra["block"] = int(args.serve_block)
+    srv = make_server(torch, sizes=cfg["sizes"], pool_cells=cfg["max_cells"], tick_ms=tick_ms, max_inflight=depth,
+                      **extra)
     # warm up every core once
     for c, p in zip(srv.cores, srv.pools):
         c.apply_Q(p[:64])
@@ -295,7 +303,8 @@ def bench(args):
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": cfg["name"], "rate_req_per_s": max(runs), "sizes": list(cfg["sizes"]),
                       "cells_per_request": "log-uniform 1..4096", "model": "hard spheres",
-                      "tick_ms": tick_ms, "launches_in_flight": depth},
+                      "tick_ms": tick_ms, "launches_in_flight": depth, "block": srv.block,
+                      "tick_rate_tflops": srv.tick_flop / (tick_ms * 1e-3) / 1e12},
            "p50_ms": main["p50_ms"], "p99_ms": main["p99_ms"], "throughput_cells_per_s": main["throughput_cells_per_s"],
            # algorithmic FLOPs of the served requests over the makespan, against the dense FP32
            # MFMA peak of 157.3 TFLOP/s; arrivals, not the device, bound it below saturation
