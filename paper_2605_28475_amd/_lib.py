@@ -123,6 +123,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not found: build it with python -m paper_2605_28475_amd.build")
+        # The device buffers and streams come from torch, which carries its own HIP runtime and
+        # names it by a different file name: loading this library first would bring in the
+        # system runtime as well, and two runtimes in one process do not share devices
+        # (the library then finds no device).  Loaded after torch, it binds to torch's.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         handle = ctypes.CDLL(LIB_PATH)
         for name, res, args in _SIGNATURES:
             fn = getattr(handle, name)
