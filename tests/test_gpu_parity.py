@@ -389,3 +389,22 @@ def test_core_self_convergence_in_padding(K, model, gamma, pad):
     say(f"[padding] K=L={K} {model} pad {pad}: max |R_pad - R_0| / max |R_0| = {err:.2e}, "
         f"worst channel {per_channel:.2e}")
     assert err < 1e-13
+
+
+def test_binding_works_before_torch_is_imported():
+    """A process that uses the binding before importing torch still finds the device: the
+    library is loaded after torch's HIP runtime, not beside a second one."""
+    import os
+    import subprocess
+    import sys
+    code = ("import paper_2605_28475_amd as w\n"
+            "c = w.Core('hs', 2, 2, device=0, precisions=('fp32',))\n"
+            "import torch\n"
+            "f = torch.zeros((3, c.N), device='cuda'); f[:, 0] = 1.0\n"
+            "q = c.apply_Q(f); torch.cuda.synchronize()\n"
+            "print('ok', float(q.abs().max()))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("[binding] subprocess without torch imported first")
+    res = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=240)
+    assert res.returncode == 0, res.stderr[-2000:]
+    assert res.stdout.strip().startswith("ok")
