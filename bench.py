@@ -261,7 +261,7 @@ def main():
     ap.add_argument("--model", default="vhs", help="profile/traffic: collision model (gamma from --gamma)")
     ap.add_argument("--fetch-dir", default=None, help="traffic: output folder of the FETCH_SIZE pass")
     ap.add_argument("--write-dir", default=None, help="traffic: output folder of the WRITE_SIZE pass")
-    ap.add_argument("--tick-ms", type=float, default=16.0, help="serve: work per scheduling tick, in ms")
+    ap.add_argument("--tick-ms", type=float, default=32.0, help="serve: work per scheduling tick, in ms")
     ap.add_argument("--serve-depth", type=int, default=2, help="serve: launches in flight")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=None, help="serve: arrival rates (req/s)")
     ap.add_argument("--serve-tflops", type=float, default=None, help="serve: rate that sizes a tick (TFLOP/s)")

@@ -93,7 +93,7 @@ class Server:
     tick_ms and rate_tflops size a tick: about tick_ms of work at rate_tflops of algorithmic
     FLOPs.  streams is accepted for compatibility: ticks run on one stream."""
 
-    def __init__(self, torch, cores, pools, budget_bytes, streams=1, max_inflight=2, device=0, tick_ms=16.0,
+    def __init__(self, torch, cores, pools, budget_bytes, streams=1, max_inflight=2, device=0, tick_ms=32.0,
                  rate_tflops=140.0, precision="fp32", pack_tiles=2, block=None):
         import paper_2605_28475_amd as wefq
         self.torch = torch
@@ -270,7 +270,7 @@ def bench(args):
     hard spheres, FP32."""
     import torch
     cfg = synth.WORKLOADS["serving"]
-    tick_ms = float(getattr(args, "tick_ms", 16.0))
+    tick_ms = float(getattr(args, "tick_ms", 32.0))
     depth = int(getattr(args, "serve_depth", 2))
     extra = {}
     if getattr(args, "serve_tflops", None):
