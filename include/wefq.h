@@ -243,17 +243,19 @@ const char* wefq_last_error(void);
 
 /* Tile shape used by wefq_apply_Q for one precision of a core: slots = output
  * states sharing the 16 MFMA columns (1, 2 or 4; the cell tile is 16/slots cells
- * and must fit in LDS), block = threads per workgroup (256, 512 or 768; 768 runs a kernel
- * instance built for 12 waves, with fewer registers per lane).  Results are bitwise
- * independent of the shape.  The default, set by wefq_build_core, is the largest tile that
- * fits in LDS with a kernel that spills at most 128 bytes of registers per lane, at 512
- * threads; 256 when a tile holds fewer than 16 work units of up to 4 output states each, and
- * 768 when the 12-wave instance spills at most 64 bytes and keeps more waves resident per
- * compute unit; the autotuner may replace it.  Each precision keeps its own shape.
+ * and must fit in LDS), block = threads per workgroup (256, 512, 768 or 1024; 768 and 1024 run
+ * kernel instances built for 12 and 16 waves, with fewer registers per lane; 1024 exists for
+ * quadrants up to 5x5, H = ceil((Kmax+1)/2) <= 5).  Results are bitwise independent of the
+ * shape.  The default, set by wefq_build_core, is the largest tile that fits in LDS with a
+ * kernel that spills at most 128 bytes of registers per lane; 256 threads when a tile holds
+ * fewer than 16 work units of up to 4 output states each, else the block among 512, 768 and
+ * 1024 whose instance spills at most 64 bytes and keeps the most waves resident per compute
+ * unit (the larger on a tie); the autotuner may replace it.  Each precision keeps its own
+ * shape.  EINVAL for an unknown precision, slots or block, or a block with no instance for
+ * the shape.
  * Setting a shape also re-derives how small batches split their tiles over workgroups
  * (a residency query of the kernel on the core's device, which the call makes current).
- * EINVAL for an unknown precision, slots or block; EUNSUPPORTED when the tile does not
- * fit in LDS; EHIP when the device cannot be selected.
+ * EUNSUPPORTED when the tile does not fit in LDS; EHIP when the device cannot be selected.
  * Not thread-safe with concurrent applies of the same core. */
 wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32_t block);
 /* The shape wefq_apply_Q currently uses for a precision.  EINVAL for a null argument or a

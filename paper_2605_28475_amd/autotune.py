@@ -14,7 +14,7 @@ import numpy as np
 from . import synth
 
 CACHE = os.environ.get("WEFQ_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "wefq", "tune.json"))
-SHAPES = [(s, b) for s in (1, 2, 4) for b in (256, 512, 768)]
+SHAPES = [(s, b) for s in (1, 2, 4) for b in (256, 512, 768, 1024)]
 
 
 def _load():

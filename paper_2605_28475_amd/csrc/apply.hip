@@ -106,7 +106,8 @@ hipError_t launch_apply_fp64(const wefq_core* h, const double* f, double* Q, int
   return hipSuccess;
 }
 
-// WAVES = 8 or 12 waves per workgroup (launches of up to 512 or 768 threads)
+// WAVES = 8, 12 or 16 waves per workgroup (launches of up to 512, 768 or 1,024 threads); 16 only
+// for quadrants up to 5x5, whose registers fit the 128 per lane of four waves per SIMD.
 template <int H, int SLOTS, int RT, int MODE, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void apply_mfma_kernel(MfmaParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -114,64 +115,61 @@ __global__ __launch_bounds__(64 * WAVES) void apply_mfma_kernel(MfmaParams p) {
   mfma_tile<H, SLOTS, RT, MODE, false, false, WAVES>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw, &unit_ctr);
 }
 
+// The instance for a block size: 8 waves up to 512 threads, 12 up to 768, 16 up to 1,024
+// (null where it does not exist).
 template <int H, int SLOTS, int RT, int MODE>
-static hipError_t launch_mfma_t(const MfmaParams& p, int64_t ntiles, int block, size_t lds, hipStream_t s) {
-  auto k = block > 512 ? apply_mfma_kernel<H, SLOTS, RT, MODE, 12> : apply_mfma_kernel<H, SLOTS, RT, MODE, 8>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3((unsigned)ntiles, (unsigned)p.nsplit), dim3(block), lds, s, p);
-  return hipGetLastError();
-}
-
-template <int H, int SLOTS, int RT, int MODE>
-static const void* kernel_t(bool wide) {
-  return wide ? (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE, 12> : (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE, 8>;
+static const void* kernel_t(int block) {
+  if (block <= 512) return (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE, 8>;
+  if (block <= 768) return (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE, 12>;
+  if constexpr (H <= 5) {
+    if (block <= 1024) return (const void*)apply_mfma_kernel<H, SLOTS, RT, MODE, 16>;
+  }
+  return nullptr;
 }
 
 // One instance per (H, slots, RT, mode, waves), chosen at run time; the launch dispatch below
 // and the attribute queries (spills, residency) see the same kernels.
 template <int H, int RT, int MODE>
-static const void* kernel_s(int slots, bool wide) {
+static const void* kernel_s(int slots, int block) {
   switch (slots) {
-    case 1: return kernel_t<H, 1, RT, MODE>(wide);
-    case 2: return kernel_t<H, 2, RT, MODE>(wide);
-    case 4: return kernel_t<H, 4, RT, MODE>(wide);
+    case 1: return kernel_t<H, 1, RT, MODE>(block);
+    case 2: return kernel_t<H, 2, RT, MODE>(block);
+    case 4: return kernel_t<H, 4, RT, MODE>(block);
     default: return nullptr;
   }
 }
 
 template <int H>
-static const void* kernel_h(int mode, int slots, int rt, bool wide) {
+static const void* kernel_h(int mode, int slots, int rt, int block) {
   if (rt == 2) {
     if constexpr (H >= 8) {
       switch (mode) {
-        case 0: return kernel_s<H, 2, 0>(slots, wide);
-        case 1: return kernel_s<H, 2, 1>(slots, wide);
-        case 2: return kernel_s<H, 2, 2>(slots, wide);
+        case 0: return kernel_s<H, 2, 0>(slots, block);
+        case 1: return kernel_s<H, 2, 1>(slots, block);
+        case 2: return kernel_s<H, 2, 2>(slots, block);
       }
     }
     return nullptr;
   }
   switch (mode) {
-    case 0: return kernel_s<H, 1, 0>(slots, wide);
-    case 1: return kernel_s<H, 1, 1>(slots, wide);
-    case 2: return kernel_s<H, 1, 2>(slots, wide);
+    case 0: return kernel_s<H, 1, 0>(slots, block);
+    case 1: return kernel_s<H, 1, 1>(slots, block);
+    case 2: return kernel_s<H, 1, 2>(slots, block);
   }
   return nullptr;
 }
 
 static const void* mfma_kernel(const wefq_core* h, int mode, int slots, int block) {
-  const bool wide = block > 512;
   switch (h->H) {
-    case 1: return kernel_h<1>(mode, slots, h->RT, wide);
-    case 2: return kernel_h<2>(mode, slots, h->RT, wide);
-    case 3: return kernel_h<3>(mode, slots, h->RT, wide);
-    case 4: return kernel_h<4>(mode, slots, h->RT, wide);
-    case 5: return kernel_h<5>(mode, slots, h->RT, wide);
-    case 6: return kernel_h<6>(mode, slots, h->RT, wide);
-    case 7: return kernel_h<7>(mode, slots, h->RT, wide);
-    case 8: return kernel_h<8>(mode, slots, h->RT, wide);
-    case 9: return kernel_h<9>(mode, slots, h->RT, wide);
+    case 1: return kernel_h<1>(mode, slots, h->RT, block);
+    case 2: return kernel_h<2>(mode, slots, h->RT, block);
+    case 3: return kernel_h<3>(mode, slots, h->RT, block);
+    case 4: return kernel_h<4>(mode, slots, h->RT, block);
+    case 5: return kernel_h<5>(mode, slots, h->RT, block);
+    case 6: return kernel_h<6>(mode, slots, h->RT, block);
+    case 7: return kernel_h<7>(mode, slots, h->RT, block);
+    case 8: return kernel_h<8>(mode, slots, h->RT, block);
+    case 9: return kernel_h<9>(mode, slots, h->RT, block);
     default: return nullptr;
   }
 }
@@ -192,38 +190,6 @@ int mfma_blocks_per_cu(const wefq_core* h, int mode, int slots, int block) {
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, block, lds) != hipSuccess)
     return 0;
   return n;
-}
-
-template <int H, int RT, int MODE>
-static hipError_t launch_mfma_s(const MfmaParams& p, int slots, int64_t ntiles, int block, size_t lds,
-                                hipStream_t s) {
-  switch (slots) {
-    case 1: return launch_mfma_t<H, 1, RT, MODE>(p, ntiles, block, lds, s);
-    case 2: return launch_mfma_t<H, 2, RT, MODE>(p, ntiles, block, lds, s);
-    case 4: return launch_mfma_t<H, 4, RT, MODE>(p, ntiles, block, lds, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int H>
-static hipError_t launch_mfma_h(const MfmaParams& p, int mode, int slots, int rt, int64_t ntiles, int block,
-                                size_t lds, hipStream_t s) {
-  if (rt == 2) {
-    if constexpr (H >= 8) {
-      switch (mode) {
-        case 0: return launch_mfma_s<H, 2, 0>(p, slots, ntiles, block, lds, s);
-        case 1: return launch_mfma_s<H, 2, 1>(p, slots, ntiles, block, lds, s);
-        case 2: return launch_mfma_s<H, 2, 2>(p, slots, ntiles, block, lds, s);
-      }
-    }
-    return hipErrorInvalidValue;
-  }
-  switch (mode) {
-    case 0: return launch_mfma_s<H, 1, 0>(p, slots, ntiles, block, lds, s);
-    case 1: return launch_mfma_s<H, 1, 1>(p, slots, ntiles, block, lds, s);
-    case 2: return launch_mfma_s<H, 1, 2>(p, slots, ntiles, block, lds, s);
-  }
-  return hipErrorInvalidValue;
 }
 
 hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, void* Q, int64_t B,
@@ -260,18 +226,12 @@ hipError_t launch_apply_mfma(const wefq_core* h, int precision, const void* f, v
     }
     return hipSuccess;
   }
-  switch (h->H) {
-    case 1: return launch_mfma_h<1>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 2: return launch_mfma_h<2>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 3: return launch_mfma_h<3>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 4: return launch_mfma_h<4>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 5: return launch_mfma_h<5>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 6: return launch_mfma_h<6>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 7: return launch_mfma_h<7>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 8: return launch_mfma_h<8>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    case 9: return launch_mfma_h<9>(p, mode, slots, h->RT, ntiles, block, lds, s);
-    default: return hipErrorInvalidValue;
-  }
+  const void* k = mfma_kernel(h, mode, slots, block);
+  if (!k) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  void* args[] = {&p};
+  return hipLaunchKernel(k, dim3((unsigned)ntiles, (unsigned)p.nsplit), dim3(block), args, lds, s);
 }
 
 // ---------------------------------------------------------------- conservation check

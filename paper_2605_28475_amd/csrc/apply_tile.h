@@ -73,8 +73,9 @@ __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
 // One cell tile: stage f, then process the (l1, q1-group) work units split, split + nsplit, ...
 // (all of them when nsplit = 1).  Each output row belongs to one unit, so splitting a tile
 // over several workgroups changes neither the work per row nor its order.
-// WAVES: waves per workgroup the instance is built for, 8 or 12 (three per SIMD, which leaves
-// each lane 168 registers: the 12-wave instances hoist the R tile only up to 6x6 quadrants).
+// WAVES: waves per workgroup the instance is built for, 8, 12 (three per SIMD, which leaves each
+// lane 168 registers: the 12-wave instances hoist the R tile only up to 6x6 quadrants) or 16
+// (four per SIMD, 128 registers; quadrants up to 5x5).
 // TWO: two inputs f, g; the coupling is symmetric, sum w (f_x (x) g_y + g_x (x) f_y), or with
 // ANTI antisymmetric, sum w (f_x (x) g_y - g_x (x) f_y), contracted with the tiles the caller
 // passes as the A operand, and the result combined as out = (out + result) / 2.

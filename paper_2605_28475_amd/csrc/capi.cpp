@@ -421,25 +421,31 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   // waves busy.  Measured with 9 to 12 units (K = L = 4 and 5; K = 8, 12, 16 at L = 2 to 4):
   // 256 threads were 1-33% faster in 18 of 20 cases and 2% slower in 2; with 16 units
   // (K = L = 6) it was mixed, with 57 (K = 4, L = 13) 1.5-1.9x slower.
-  // Otherwise 768 threads (12 waves, three per SIMD) where the 12-wave instance of the mode's
-  // tile shape spills at most 64 bytes per lane and keeps more waves resident per compute unit
-  // than 8-wave workgroups; else 512.  A tile that fills the LDS leaves one workgroup per
-  // compute unit, and the third wave per SIMD hides more of the coupling's gather latency
-  // behind the other waves' arithmetic.  Measured (ms, 512 -> 768 threads): K = L = 12 FP32
-  // 65,536 cells 39.6 -> 37.3, BF16x3 31.3 -> 30.9; K = L = 10 FP32 32,768 cells 7.63 -> 6.89;
-  // K = L = 14 FP32 16,384 cells 29.0 -> 24.7; K = L = 16 FP32 62.9 -> 59.1 (a 56-byte spill);
-  // K = L = 8 FP64 65,536 cells 7.68 -> 6.83.  Where two 8-wave workgroups fit (K = L = 8 in
-  // FP32) 768 threads were slower (3.66 -> 4.07 ms), and instances that spill more were much
-  // slower (K = L = 12 FP64: 77.0 -> 91.3 ms).
+  // Otherwise the block of 512, 768 (12 waves, three per SIMD) or 1,024 threads (16 waves, four
+  // per SIMD; quadrants up to 5x5) whose instance of the mode's tile shape spills at most 64
+  // bytes per lane and keeps the most waves resident per compute unit, the larger block on a
+  // tie.  A tile that fills the LDS leaves one workgroup per compute unit, and the third wave
+  // per SIMD hides more of the coupling's gather latency behind the other waves' arithmetic;
+  // where several workgroups fit, one larger workgroup stages each tile once and its waves share
+  // one work-unit counter.  Measured (ms, 512 -> 768 threads): K = L = 12 FP32 65,536 cells
+  // 39.6 -> 37.3, BF16x3 31.3 -> 30.9; K = L = 10 FP32 32,768 cells 7.63 -> 6.89; K = L = 14 FP32
+  // 16,384 cells 29.0 -> 24.7; K = L = 16 FP32 62.9 -> 59.1 (a 56-byte spill); K = L = 8 FP64
+  // 65,536 cells 7.68 -> 6.83.  Instances that spill more were much slower (K = L = 12 FP64:
+  // 77.0 -> 91.3 ms).  At K = L = 8 in FP32, where two 8-wave workgroups fit, 768 threads were
+  // slower (3.66 -> 4.07 ms) and 1,024 equal at 65,536 cells (3.65 ms) and faster on small
+  // batches (4,096 cells 0.291 -> 0.278 ms, 2,048 cells 0.192 -> 0.162 ms).
   constexpr int kWideMaxSpill = 64;
   for (int mode = 0; mode < 3; ++mode) {
     int blk = h->nunits < 16 ? 256 : 512;
     if (blk == 512 && h->slots[mode]) {
       const int sl = h->slots[mode];
-      const int spill = mfma_spill_bytes(h, mode, sl, 768);
-      const int waves8 = 8 * mfma_blocks_per_cu(h, mode, sl, 512);
-      const int waves12 = 12 * mfma_blocks_per_cu(h, mode, sl, 768);
-      if (spill >= 0 && spill <= kWideMaxSpill && waves12 > waves8) blk = 768;
+      int best = 8 * mfma_blocks_per_cu(h, mode, sl, 512);
+      for (const int cand : {768, 1024}) {
+        const int spill = mfma_spill_bytes(h, mode, sl, cand);
+        if (spill < 0 || spill > kWideMaxSpill) continue;          // no instance, or it spills
+        const int waves = cand / 64 * mfma_blocks_per_cu(h, mode, sl, cand);
+        if (waves >= best) { best = waves; blk = cand; }
+      }
     }
     h->block[mode] = blk;
     h->split_per_cu[mode] = split_target(h, mode);
@@ -835,12 +841,15 @@ wefq_status wefq_tune_set(wefq_handle h, int32_t precision, int32_t slots, int32
   const int mode = mfma_mode(precision);
   if (mode < 0) return fail(WEFQ_EINVAL, "tile shapes exist for FP64, FP32 and BF16X3");
   if (slots != 1 && slots != 2 && slots != 4) return fail(WEFQ_EINVAL, "slots must be 1, 2 or 4");
-  if (block != 256 && block != 512 && block != 768) return fail(WEFQ_EINVAL, "block must be 256, 512 or 768");
+  if (block != 256 && block != 512 && block != 768 && block != 1024)
+    return fail(WEFQ_EINVAL, "block must be 256, 512, 768 or 1024");
   const size_t elem = mode == 2 ? 8 : 4;
   if (tile_lds_bytes(h, slots, elem) > (size_t)h->lds_limit)
     return fail(WEFQ_EUNSUPPORTED, "tile of 16/slots cells does not fit in LDS");
-  // the residency queries below run on the current device
+  // the attribute and residency queries below run on the current device
   if (hipSetDevice(h->device) != hipSuccess) return fail(WEFQ_EHIP, "hipSetDevice failed");
+  if (mfma_spill_bytes(h, mode, slots, block) < 0)
+    return fail(WEFQ_EINVAL, "no kernel instance for this tile shape at this block size (1024: quadrants up to 5x5)");
   h->slots[mode] = slots;
   h->block[mode] = block;
   h->split_per_cu[mode] = split_target(h, mode);

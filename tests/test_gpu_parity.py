@@ -125,9 +125,9 @@ def test_cell_result_independent_of_batch(prec):
 @pytest.mark.parametrize("K", [3, 5, 8, 10, 12, 14, 16])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
 def test_wide_workgroups_bitwise_equal(K, prec):
-    """The 12-wave kernel instances (768 threads; the R tile is not hoisted from 7x7
-    quadrants up) give bitwise the results of the 8-wave instances, at the default tile shape
-    and at one other."""
+    """The 12- and 16-wave kernel instances (768 and 1,024 threads; the R tile is not hoisted
+    from 7x7 quadrants up under 12 waves; 16 waves for quadrants up to 5x5) give bitwise the
+    results of the 8-wave instances, at the default tile shape and at one other."""
     core = gpu_core("hs", K, K, 1.0)
     old = core.tune_get(prec)
     B = 40 if K >= 14 else 100
@@ -140,9 +140,10 @@ def test_wide_workgroups_bitwise_equal(K, prec):
             except wefq.WefqError:
                 continue                                  # tile does not fit in LDS
             narrow = run(core, c, prec)
-            core.tune_set(prec, slots, 768)
-            wide = run(core, c, prec)
-            assert np.array_equal(narrow, wide), slots
+            for block in (768, 1024) if (K + 2) // 2 <= 5 else (768,):
+                core.tune_set(prec, slots, block)
+                wide = run(core, c, prec)
+                assert np.array_equal(narrow, wide), (slots, block)
     finally:
         core.tune_set(prec, *old)
 
