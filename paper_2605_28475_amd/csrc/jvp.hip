@@ -18,17 +18,19 @@
 namespace wefq {
 
 // FP32 launches run 12 waves per workgroup (768 threads, three per SIMD; the two cell tiles
-// fill the LDS, so one workgroup holds a compute unit), FP64 launches 8.  Measured on one
-// MI355X, J(c) d in FP32, 8 -> 12 waves: K = L = 12 with 65,536 cells 66.4 -> 62.4 ms, K = L = 16
-// with 8,192 cells 59.2 -> 51.3 ms, K = L = 8 with 65,536 cells 7.08 -> 6.02 ms, K = L = 10 and
-// 14 11% and 10% faster; in FP64 the 12-wave instances spill.
-template <int MODE> constexpr int jvp_waves() { return MODE == 0 ? 12 : 8; }
+// fill the LDS, so one workgroup holds a compute unit), 16 up to 5x5 quadrants (1,024 threads,
+// four per SIMD, whose registers fit 128); FP64 launches 8.  Measured on one MI355X, J(c) d in
+// FP32, 8 -> 12 waves: K = L = 12 with 65,536 cells 66.4 -> 62.4 ms, K = L = 16 with 8,192 cells
+// 59.2 -> 51.3 ms, K = L = 8 with 65,536 cells 7.08 -> 6.02 ms, K = L = 10 and 14 11% and 10%
+// faster; 12 -> 16 waves: K = L = 8 6.06 -> 5.72 ms, K = L = 9 with 32,768 cells 4.86 -> 4.59 ms,
+// K = L = 6 equal; in FP64 the 12-wave instances spill.
+template <int H, int MODE> constexpr int jvp_waves() { return MODE == 0 ? (H <= 5 ? 16 : 12) : 8; }
 
 template <int H, int SLOTS, int RT, int MODE, bool ANTI>
-__global__ __launch_bounds__(64 * jvp_waves<MODE>()) void apply_jvp_kernel(MfmaParams p) {
+__global__ __launch_bounds__((64 * jvp_waves<H, MODE>())) void apply_jvp_kernel(MfmaParams p) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int unit_ctr;
-  mfma_tile<H, SLOTS, RT, MODE, true, ANTI, jvp_waves<MODE>()>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw,
+  mfma_tile<H, SLOTS, RT, MODE, true, ANTI, jvp_waves<H, MODE>()>(p, (int64_t)blockIdx.x, (int)blockIdx.y, lds_raw,
                                                                &unit_ctr);
 }
 
@@ -37,7 +39,7 @@ static hipError_t launch_jvp_t(const MfmaParams& p, bool anti, int64_t ntiles, s
   auto k = anti ? apply_jvp_kernel<H, SLOTS, RT, MODE, true> : apply_jvp_kernel<H, SLOTS, RT, MODE, false>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3((unsigned)ntiles, (unsigned)p.nsplit), dim3(64 * jvp_waves<MODE>()), lds, s, p);
+  hipLaunchKernelGGL(k, dim3((unsigned)ntiles, (unsigned)p.nsplit), dim3((64 * jvp_waves<H, MODE>())), lds, s, p);
   return hipGetLastError();
 }
 
@@ -104,7 +106,7 @@ static hipError_t launch_two(const wefq_core* h, bool anti, int precision, const
   const size_t lds = 2 * tile_lds_bytes(h, slots, elem);
   // a launch holds at most 2^32 - 1 threads: larger batches run as several launches of whole
   // tiles (each cell's result does not depend on its batch)
-  const int64_t max_cells = max_cells_per_launch(TB, mode == 0 ? 64 * jvp_waves<0>() : 64 * jvp_waves<2>());
+  const int64_t max_cells = max_cells_per_launch(TB, 1024);   // the largest block of any instance
   if (B > max_cells) {
     for (int64_t c0 = 0; c0 < B; c0 += max_cells) {
       const int64_t nc = (B - c0) < max_cells ? (B - c0) : max_cells;
