@@ -26,7 +26,7 @@ PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense
 
 
 KERNEL_SOURCES = ["paper_2605_28475_amd/csrc/apply_tile.h", "paper_2605_28475_amd/csrc/apply.hip",
-                  "paper_2605_28475_amd/csrc/capi.cpp"]
+                  "paper_2605_28475_amd/csrc/capi.cpp", "paper_2605_28475_amd/csrc/wefq_core.h"]
 
 
 def kernel_source_hash():

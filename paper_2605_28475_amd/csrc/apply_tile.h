@@ -29,7 +29,7 @@ struct MfmaParams {
   const int* spair;        // per slice: first single row; rows [sptr[s], spair[s]) are q2 pairs
   const uint32_t* mq;      // [rows][2]: q2*NKp, q3*NKp, the LDS row offsets of the two gathered states
                            // (swapped in the second row of a pair: a pair reads as u, a, b, u)
-  const uint32_t* mq_pad;  // the same with the padded row pitch (16-cell tiles with a pad row)
+  const uint32_t* mq_pad;  // the same with the padded row pitch (tiles with a pad row per block)
   const float* mg;         // merged weights (FP32 / BF16X3)
   const double* mg64;      // merged weights (FP64)
   const float* Rt32;       // [NTm][ceil(H*H/4)][64][4]: rows k1 < 16 in the MFMA A-operand
@@ -76,10 +76,12 @@ __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
 // WAVES: waves per workgroup the instance is built for, 8, 12 (three per SIMD, which leaves each
 // lane 168 registers: the 12-wave instances hoist the R tile only up to 6x6 quadrants) or 16
 // (four per SIMD, 128 registers; quadrants up to 5x5).
+// PAD_ALL: the tile layout's pad rows in tiles of every width (false: 16-cell tiles only).
 // TWO: two inputs f, g; the coupling is symmetric, sum w (f_x (x) g_y + g_x (x) f_y), or with
 // ANTI antisymmetric, sum w (f_x (x) g_y - g_x (x) f_y), contracted with the tiles the caller
 // passes as the A operand, and the result combined as out = (out + result) / 2.
-template <int H, int SLOTS, int RT, int MODE, bool TWO = false, bool ANTI = false, int WAVES = 8>
+template <int H, int SLOTS, int RT, int MODE, bool TWO = false, bool ANTI = false, int WAVES = 8,
+          bool PAD_ALL = true>
 __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int split, unsigned char* lds_raw,
                                           int* unit_ctr_p) {
   typedef typename ModeTraits<MODE>::T T;
@@ -103,7 +105,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   // stage the coefficient tile: fs[(q * NKp + k + pd * (k >= H)) * TB + cell], with the
   // zero pad and tail rows of the layout described with tile_upper_row
   // (with two inputs the second tile follows the first, gofs elements later)
-  const int pd = tile_pad_rows(NK, H, TB);
+  const int pd = tile_pad_rows(NK, H, TB, PAD_ALL);
   const int NKp = NK + pd;
   const int tail = tile_tail_rows(NK, H);
   const int gofs = TWO ? (p.NQ * NKp + tail) * TB : 0;
@@ -135,7 +137,7 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
   // q block: the lower half starts at row 0, the upper half at tile_upper_row (the R
   // tile gives zero weight to its rows outside [H, NK)), so every gather is a per-lane
   // base plus a compile-time offset.
-  const int up = tile_upper_row(NK, H, TB);
+  const int up = tile_upper_row(NK, H, TB, PAD_ALL);
   const int k2s = h2 ? up : 0, k3s = h3 ? up : 0;
   const T* lane_u = fs + k2s * TB + cellj;
   const T* lane_w = fs + k3s * TB + cellj;

@@ -255,7 +255,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   };
   const std::vector<uint32_t> mq_rows = unpack_rows((uint32_t)NK);
   std::vector<uint32_t> mq_pad;
-  if (tile_pad_rows(NK, (NK + 1) / 2, 16)) mq_pad = unpack_rows((uint32_t)(NK + 1));
+  if (tile_pad_rows(NK, (NK + 1) / 2, 8)) mq_pad = unpack_rows((uint32_t)(NK + 1));
   // MFMA geometry
   h->H = (NK + 1) / 2;
   h->RT = NK > 16 ? 2 : 1;

@@ -9,8 +9,10 @@
 // runs as many workgroups as fit on the device at once; each pulls items from
 // a device counter and runs the same per-tile code as the standalone apply
 // (same arithmetic order, hence bitwise the same per-cell results), selecting
-// the tile geometry of the item's core.  plan_reset_kernel clears the counter
-// (a kernel node, so replays of the captured graph need no memset node).
+// the tile geometry of the item's core (8- and 4-cell tiles of even NK and even H
+// without the standalone layout's pad rows: only LDS addresses differ).
+// plan_reset_kernel clears the counter (a kernel node, so replays of the captured
+// graph need no memset node).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,9 +44,9 @@ __global__ void plan_reset_kernel(int* counter) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
-#define WEFQ_TILE_CASE(H_, S_, R_)                                       \
-  case (H_) * 100 + (S_) * 10 + (R_):                                    \
-    mfma_tile<H_, S_, R_, MODE>(sd.p, tile, split, lds_raw, &unit_ctr);  \
+#define WEFQ_TILE_CASE(H_, S_, R_)                                                              \
+  case (H_) * 100 + (S_) * 10 + (R_):                                                           \
+    mfma_tile<H_, S_, R_, MODE, false, false, 8, false>(sd.p, tile, split, lds_raw, &unit_ctr); \
     break;
 #define WEFQ_TILE_CASES_H(H_) WEFQ_TILE_CASE(H_, 1, 1) WEFQ_TILE_CASE(H_, 2, 1) WEFQ_TILE_CASE(H_, 4, 1)
 
@@ -172,7 +174,7 @@ static wefq_status describe_segments(int32_t nseg, const wefq_segment* segs, Wor
     int slots = g.slots ? g.slots : h->slots[mode];
     if (slots != 1 && slots != 2 && slots != 4) return plan_fail(WEFQ_EINVAL, "slots must be 0, 1, 2 or 4");
     const int TB = 16 / slots;
-    const size_t need = tile_lds_bytes(h, slots, elem);
+    const size_t need = tile_lds_bytes(h, slots, elem, false);
     if (need > (size_t)h->lds_limit) return plan_fail(WEFQ_EUNSUPPORTED, "segment tile does not fit in LDS");
     w.lds = std::max(w.lds, need);
     SegDesc& d = w.descs[i];

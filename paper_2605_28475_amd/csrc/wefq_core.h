@@ -52,7 +52,7 @@ struct wefq_core {
   int* d_sptr = nullptr;               // NSm(all (c,m1)) + 1
   int* d_spair = nullptr;              // per slice: first single row (rows before it come in q2 pairs)
   uint32_t* d_mq = nullptr;            // merged entries, two words each: q2*NK, q3*NK
-  uint32_t* d_mq_pad = nullptr;        // the same with the padded pitch NK+1 (16-cell tiles)
+  uint32_t* d_mq_pad = nullptr;        // the same with the padded pitch NK+1 (tiles with pad rows)
   float* d_mg = nullptr;               // merged weights
   double* d_mg64 = nullptr;            // merged weights, FP64
   float* d_Rt32 = nullptr;             // [NTm][ceil(H*H/4)][64][4]  (rows k1 < 16)
@@ -99,15 +99,19 @@ constexpr int UNIT_STRIDE = 10;
 //    tail row;
 //  * odd NK, even H: it starts at k = NK - H = H - 1; that first row, shared with the
 //    lower half, has zero weight;
-//  * even NK: it starts at k = H; when H is even and TB = 16, one zero pad row per block
-//    sits between k = H - 1 and k = H.
-__host__ __device__ inline int tile_pad_rows(int NK, int H, int TB) {
-  return (TB == 16 && !(NK & 1) && !(H & 1)) ? 1 : 0;
+//  * even NK: it starts at k = H; when H is even, one zero pad row per block sits between
+//    k = H - 1 and k = H, which also makes the block pitch NK + 1 odd (the rows of different
+//    output states' q blocks then fall into different banks as often as odd NK allows).
+//    every_tile = false keeps the pad to 16-cell tiles: the persistent plan kernel, whose
+//    one body holds every tile shape, measured slower with the pad code in its 8- and
+//    4-cell shapes.
+__host__ __device__ inline int tile_pad_rows(int NK, int H, int TB, bool every_tile = true) {
+  return (!(NK & 1) && !(H & 1) && (every_tile || TB == 16)) ? 1 : 0;
 }
 __host__ __device__ inline int tile_tail_rows(int NK, int H) { return ((NK & 1) && (H & 1)) ? 1 : 0; }
 __host__ __device__ inline int tile_upper_k(int NK, int H) { return ((NK & 1) && !(H & 1)) ? NK - H : H; }
-__host__ __device__ inline int tile_upper_row(int NK, int H, int TB) {
-  return tile_upper_k(NK, H) + tile_pad_rows(NK, H, TB);
+__host__ __device__ inline int tile_upper_row(int NK, int H, int TB, bool every_tile = true) {
+  return tile_upper_k(NK, H) + tile_pad_rows(NK, H, TB, every_tile);
 }
 
 // Output states per work unit, for every quadrant size.  Units of 4 states give each wave
@@ -173,9 +177,9 @@ inline int mfma_mode(int precision) {
 }
 
 // LDS bytes of one coefficient tile of 16/slots cells.
-inline size_t tile_lds_bytes(const wefq_core* h, int slots, size_t elem) {
+inline size_t tile_lds_bytes(const wefq_core* h, int slots, size_t elem, bool every_tile = true) {
   const int TB = 16 / slots;
-  const int pd = tile_pad_rows(h->NK, h->H, TB);
+  const int pd = tile_pad_rows(h->NK, h->H, TB, every_tile);
   return ((size_t)h->NQ * (h->NK + pd) + tile_tail_rows(h->NK, h->H)) * TB * elem;
 }
 

@@ -61,6 +61,32 @@ def test_plan_matches_single_segment_applies(prec):
     plan.close()
 
 
+@pytest.mark.parametrize("prec,slots", [("fp32", 2), ("fp32", 4), ("fp64", 2), ("fp64", 4)])
+def test_plan_tiles_without_pad_rows_match_padded_standalone_tiles(prec, slots):
+    """8- and 4-cell tiles of even NK and even H (K = 3, 7, 15): the standalone kernels stage
+    them with a pad row per q block, the persistent kernel without.  Only LDS addresses
+    differ, so the results are bitwise equal."""
+    specs = [("hs", 3, None, 29), ("vhs", 7, 0.5, 21)]
+    if not (prec == "fp64" and slots == 2):          # (that K = 15 tile does not fit in LDS)
+        specs.append(("hs", 15, None, 6))
+    say(f"[plan pad] {prec} slots={slots}")
+    segs = segments(prec, specs)
+    refs = []
+    for c, f, _ in segs:
+        old = c.tune_get(prec)
+        c.tune_set(prec, slots, old[1])
+        try:
+            refs.append(c.apply_Q(f, precision=prec).clone())
+        finally:
+            c.tune_set(prec, *old)
+    plan = wefq.Plan([(c, f, q, slots) for c, f, q in segs], precision=prec)
+    plan.launch()
+    torch.cuda.synchronize()
+    for (c, _, q), r in zip(segs, refs):
+        assert torch.equal(q, r), f"K={c.K}"
+    plan.close()
+
+
 def test_plan_tile_shape_override_keeps_results():
     segs = segments("fp32", [("hs", 4, None, 40), ("vhs", 8, 0.5, 23)])
     refs = [c.apply_Q(f).clone() for c, f, _ in segs]
