@@ -240,7 +240,7 @@ bool prepare_apply_tables(wefq_core* h, const std::vector<CooRow>& coo, hipStrea
   h->NSm = nsm;
   // The device tables hold each row's two LDS row offsets as words of their own (q2*pitch,
   // q3*pitch), so that the kernel forms an address with one shift-and-add; the pitch is NK,
-  // and NK+1 for 16-cell tiles with a pad row per q block.  The second row of a pair stores
+  // and NK+1 for tiles with a pad row per q block.  The second row of a pair stores
   // its two words swapped (q3b first), so that a pair's three distinct offsets u = q2, a =
   // q3a, b = q3b are its first three words and come in one load.
   auto unpack_rows = [&](uint32_t pitch) {
