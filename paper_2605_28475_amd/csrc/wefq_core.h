@@ -102,9 +102,9 @@ constexpr int UNIT_STRIDE = 10;
 //  * even NK: it starts at k = H; when H is even, one zero pad row per block sits between
 //    k = H - 1 and k = H, which also makes the block pitch NK + 1 odd (the rows of different
 //    output states' q blocks then fall into different banks as often as odd NK allows).
-//    every_tile = false keeps the pad to 16-cell tiles: the persistent plan kernel, whose
-//    one body holds every tile shape, measured slower with the pad code in its 8- and
-//    4-cell shapes.
+//    every_tile = false keeps the pad to 16-cell tiles (the halves of 8- and 4-cell tiles
+//    are then H rows apart): the persistent plan kernel, whose one body holds every tile
+//    shape, measured slower with the pad code in its 8- and 4-cell shapes.
 __host__ __device__ inline int tile_pad_rows(int NK, int H, int TB, bool every_tile = true) {
   return (!(NK & 1) && !(H & 1) && (every_tile || TB == 16)) ? 1 : 0;
 }
