@@ -52,8 +52,8 @@ def test_jvp_matches_oracle(K, L, model, gamma, B, prec):
     assert np.all(got[:, invariant_indices(K, L)] == 0.0)
 
 
-@pytest.mark.parametrize("K,L,model,gamma", [(12, 12, "vhs", 0.5), (13, 13, "mm", 0.0), (14, 14, "hs", 1.0),
-                                             (16, 16, "hs", 1.0)])
+@pytest.mark.parametrize("K,L,model,gamma", [(11, 11, "vhs", 0.5), (12, 12, "vhs", 0.5), (13, 13, "mm", 0.0),
+                                             (14, 14, "hs", 1.0), (15, 15, "hs", 1.0), (16, 16, "hs", 1.0)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_jvp_polarization_large(K, L, model, gamma, prec):
     """At sizes the oracle does not reach in seconds: J(c) d = Q(c + d) - Q(c) - Q(d), with
@@ -176,7 +176,7 @@ def test_bilinear_needs_prepared_tables():
     core.close()
 
 
-@pytest.mark.parametrize("K,L", [(13, 13), (16, 16)])
+@pytest.mark.parametrize("K,L", [(13, 13), (15, 15), (16, 16)])
 def test_bilinear_large_fp64_against_fp32_and_identities(K, L):
     """FP64 Q(f, g) where it runs on tiles of 2 cells: Q(f, f) = Q(f) (the FP64 apply),
     Q(f, g) + Q(g, f) = J(f) g, and agreement with the FP32 bilinear form."""
