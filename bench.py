@@ -265,7 +265,8 @@ def main():
     ap.add_argument("--serve-depth", type=int, default=2, help="serve: launches in flight")
     ap.add_argument("--serve-rates", type=float, nargs="*", default=None, help="serve: arrival rates (req/s)")
     ap.add_argument("--serve-tflops", type=float, default=None, help="serve: rate that sizes a tick (TFLOP/s)")
-    ap.add_argument("--serve-block", type=int, default=None, help="serve: threads per workgroup (256 or 512)")
+    ap.add_argument("--serve-block", type=int, default=None,
+                    help="serve: threads per workgroup (256, 512 or 768; default 768 in FP32)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of f (known byte count) for counter scaling")
     args = ap.parse_args()

@@ -282,7 +282,11 @@ typedef struct {
  * workgroups pull items from a device counter; the counter
  * reset and the kernel are captured once in a HIP graph.  Per-cell results equal
  * those of wefq_apply_Q bitwise.  Buffers and cores must outlive the plan; the plan
- * owns a small device work list.  Synchronizes stream. */
+ * owns a small device work list.  Synchronizes stream.  block: 256 or 512 threads (the
+ * 8-wave kernel, every tile shape), or 768 (the 12-wave kernel, three waves per SIMD: FP32
+ * plans whose segments all have quadrants up to 5x5 or 7x7 with one output state per MFMA
+ * column group, or 9x9 with two, the default FP32 shapes of K = 0..9, 12 and 16; EINVAL
+ * otherwise). */
 wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t block, void* stream,
                              wefq_plan* out);
 /* Replay the captured graph on stream (asynchronous).  Concurrent launches of one
@@ -306,8 +310,10 @@ typedef struct wefq_runner_s* wefq_runner;
  * next (the spatial batching of Section 4.5 over requests of several truncations and models).
  * It owns a ring of 4 slots, each a device work list of max_segments descriptors and max_items
  * work items with a pinned host staging copy.  precision: FP32, BF16X3 or FP64 for every
- * segment; block: 256 or 512 threads.  EINVAL for bad arguments, ENOMEM when the slots cannot
- * be allocated. */
+ * segment; block: 256, 512 or 768 threads (768: FP32 only, the 12-wave kernel of
+ * wefq_plan_create for launches whose segments all have its tile shapes, the 8-wave kernel of
+ * 512 threads for the others).  EINVAL for bad arguments, ENOMEM when the slots cannot be
+ * allocated. */
 wefq_status wefq_runner_create(int32_t device, int32_t precision, int32_t max_segments, int32_t max_items,
                                int32_t block, wefq_runner* out);
 

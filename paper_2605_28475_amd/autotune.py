@@ -86,7 +86,7 @@ def _time_plan(plan, stream, reps):
     return float(np.median([a.elapsed_time(e) for a, e in evs]))
 
 
-def tune_plan(segments, precision="fp32", blocks=(512, 256), reps=3):
+def tune_plan(segments, precision="fp32", blocks=(512, 768, 256), reps=3):
     """Tile shapes for a whole uneven batch, chosen by timing whole plans (graph replays), not
     segments alone: a shape that wins for a core on its own can lose inside the mix, where
     the persistent kernel's LDS size and residency are set by the largest tile and the work
@@ -94,7 +94,9 @@ def tune_plan(segments, precision="fp32", blocks=(512, 256), reps=3):
 
     segments: list of (core, f, Q).  Coordinate descent: start from every core's default shape
     at the first block size; then, core by core in decreasing share of the plan's FLOPs, try
-    every slots value with the others held, keeping the fastest; then every block size.
+    every slots value with the others held, keeping the fastest; then every other block size,
+    with those shapes and with the default ones (768 threads: FP32 plans of the 12-wave kernel's
+    tile shapes only; other candidates that cannot be built are skipped).
     Returns (slots per segment, block, {candidate: ms}); per-cell results do not depend on it."""
     import torch
     from . import Plan, WefqError
@@ -109,8 +111,8 @@ def tune_plan(segments, precision="fp32", blocks=(512, 256), reps=3):
             try:
                 plan = Plan([(c, f, q, s) for (c, f, q), s in zip(segments, sl)], precision=precision, block=blk)
             except WefqError:
-                timings[key] = float("inf")        # a tile that does not fit in LDS
-                return timings[key]
+                timings[key] = float("inf")        # a tile that does not fit in LDS, or a shape
+                return timings[key]                # that the block size does not take
             timings[key] = _time_plan(plan, stream, reps)
             plan.close()
         return timings[key]
@@ -125,8 +127,12 @@ def tune_plan(segments, precision="fp32", blocks=(512, 256), reps=3):
             t = measure(trial, block)
             if t < best:
                 best, slots = t, trial
+    # every other block size, with the tuned shapes and with the default ones (the 12-wave
+    # kernel of 768 threads takes only some tile shapes, which the default ones may be)
+    start = list(slots)
     for blk in blocks[1:]:
-        t = measure(slots, blk)
-        if t < best:
-            best, block = t, blk
+        for sl in (start, [0] * len(segments)):
+            t = measure(sl, blk)
+            if t < best:
+                best, block, slots = t, blk, list(sl)
     return slots, block, timings

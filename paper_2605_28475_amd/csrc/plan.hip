@@ -44,14 +44,23 @@ __global__ void plan_reset_kernel(int* counter) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
-#define WEFQ_TILE_CASE(H_, S_, R_)                                                              \
-  case (H_) * 100 + (S_) * 10 + (R_):                                                           \
-    mfma_tile<H_, S_, R_, MODE, false, false, 8, false>(sd.p, tile, split, lds_raw, &unit_ctr); \
+#define WEFQ_TILE_CASE(H_, S_, R_)                                                                 \
+  case (H_) * 100 + (S_) * 10 + (R_):                                                              \
+    mfma_tile<H_, S_, R_, MODE, false, false, WAVES, false>(sd.p, tile, split, lds_raw, &unit_ctr); \
     break;
 #define WEFQ_TILE_CASES_H(H_) WEFQ_TILE_CASE(H_, 1, 1) WEFQ_TILE_CASE(H_, 2, 1) WEFQ_TILE_CASE(H_, 4, 1)
 
-template <int MODE>
-__global__ __launch_bounds__(512) void apply_persistent_kernel(PlanParams pp) {
+// Tile shapes of the 12-wave persistent kernel (768 threads, three waves per SIMD, 168
+// registers): FP32 quadrants up to 5x5 and 7x7 with one output state per column group, and 9x9
+// with two and the 17th radial row (the default FP32 shapes of K = 0..9, 12 and 16).  One kernel
+// body holding these shapes compiles without register spill; adding 6x6 spilled 32 bytes per
+// lane, adding 7x7 and 8x8 with two output states 100.
+__host__ __device__ constexpr bool wide_plan_shape(int H, int SLOTS, int RT) {
+  return (SLOTS == 1 && RT == 1 && (H <= 5 || H == 7)) || (H == 9 && SLOTS == 2 && RT == 2);
+}
+
+template <int MODE, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void apply_persistent_kernel(PlanParams pp) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int unit_ctr;
   __shared__ int item_sh;
@@ -65,13 +74,21 @@ __global__ __launch_bounds__(512) void apply_persistent_kernel(PlanParams pp) {
     const SegDesc& sd = pp.segs[(int)(code >> 48)];
     const int split = (int)((code >> 40) & 0xff);
     const int64_t tile = code & ((1LL << 40) - 1);
-    switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
-      WEFQ_TILE_CASES_H(1) WEFQ_TILE_CASES_H(2) WEFQ_TILE_CASES_H(3)
-      WEFQ_TILE_CASES_H(4) WEFQ_TILE_CASES_H(5) WEFQ_TILE_CASES_H(6)
-      WEFQ_TILE_CASES_H(7) WEFQ_TILE_CASES_H(8) WEFQ_TILE_CASES_H(9)
-      WEFQ_TILE_CASE(8, 1, 2) WEFQ_TILE_CASE(8, 2, 2) WEFQ_TILE_CASE(8, 4, 2)
-      WEFQ_TILE_CASE(9, 1, 2) WEFQ_TILE_CASE(9, 2, 2) WEFQ_TILE_CASE(9, 4, 2)
-      default: break;
+    if constexpr (WAVES == 12) {
+      switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
+        WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
+        WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(7, 1, 1) WEFQ_TILE_CASE(9, 2, 2)
+        default: break;
+      }
+    } else {
+      switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
+        WEFQ_TILE_CASES_H(1) WEFQ_TILE_CASES_H(2) WEFQ_TILE_CASES_H(3)
+        WEFQ_TILE_CASES_H(4) WEFQ_TILE_CASES_H(5) WEFQ_TILE_CASES_H(6)
+        WEFQ_TILE_CASES_H(7) WEFQ_TILE_CASES_H(8) WEFQ_TILE_CASES_H(9)
+        WEFQ_TILE_CASE(8, 1, 2) WEFQ_TILE_CASE(8, 2, 2) WEFQ_TILE_CASE(8, 4, 2)
+        WEFQ_TILE_CASE(9, 1, 2) WEFQ_TILE_CASE(9, 2, 2) WEFQ_TILE_CASE(9, 4, 2)
+        default: break;
+      }
     }
     __syncthreads();                 // the tile's LDS is reused by the next item
   }
@@ -111,23 +128,25 @@ static void plan_free(wefq_plan_s* p) {
   delete p;
 }
 
+// Kernel of a plan precision (mode 0 FP32, 1 BF16X3, 2 FP64) and block size (768 threads: the
+// 12-wave FP32 kernel).
+static const void* persistent_kernel(int mode, int block) {
+  if (block == 768) return (const void*)apply_persistent_kernel<0, 12>;
+  return mode == 0 ? (const void*)apply_persistent_kernel<0, 8>
+         : mode == 1 ? (const void*)apply_persistent_kernel<1, 8> : (const void*)apply_persistent_kernel<2, 8>;
+}
+
+static hipError_t launch_persistent(int mode, int block, int grid, size_t lds, hipStream_t s, PlanParams pp) {
+  void* args[] = {&pp};
+  hipError_t e = hipLaunchKernel(persistent_kernel(mode, block), dim3(grid), dim3(block), args, lds, s);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
 static hipError_t plan_enqueue(const wefq_plan_s* p, hipStream_t s) {
   hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, s, p->d_counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  PlanParams pp{p->d_segs, p->d_items, p->nitems, p->d_counter};
-  switch (p->mode) {
-    case 0: hipLaunchKernelGGL(apply_persistent_kernel<0>, dim3(p->grid), dim3(p->block), p->lds, s, pp); break;
-    case 1: hipLaunchKernelGGL(apply_persistent_kernel<1>, dim3(p->grid), dim3(p->block), p->lds, s, pp); break;
-    default: hipLaunchKernelGGL(apply_persistent_kernel<2>, dim3(p->grid), dim3(p->block), p->lds, s, pp); break;
-  }
-  return hipGetLastError();
-}
-
-// Kernel of a plan precision (mode 0 FP32, 1 BF16X3, 2 FP64).
-static const void* persistent_kernel(int mode) {
-  return mode == 0 ? (const void*)apply_persistent_kernel<0>
-         : mode == 1 ? (const void*)apply_persistent_kernel<1> : (const void*)apply_persistent_kernel<2>;
+  return launch_persistent(p->mode, p->block, p->grid, p->lds, s, PlanParams{p->d_segs, p->d_items, p->nitems, p->d_counter});
 }
 
 // A batch of segments made into a work list: the per-segment parameters and the item codes,
@@ -139,6 +158,14 @@ struct WorkList {
   std::vector<SegDesc> descs;
   std::vector<int64_t> codes;
 };
+
+// Whether every segment of an FP32 work list has a tile shape of the 12-wave kernel.
+static bool all_wide(const WorkList& w) {
+  if (w.mode != 0) return false;
+  for (const SegDesc& d : w.descs)
+    if (!wide_plan_shape(d.H, d.SLOTS, d.RT)) return false;
+  return true;
+}
 
 // Validate the segments and build their descriptors (any mix of cores of one precision on one
 // device).  Items are made by make_items once the residency is known.
@@ -231,7 +258,7 @@ static wefq_status make_items(WorkList& w, const std::vector<int64_t>& seg_tiles
 static void residency(int mode, int block, size_t lds, int device, int* per_cu, int* cus) {
   *per_cu = 0;
   *cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, persistent_kernel(mode), block, lds) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, persistent_kernel(mode, block), block, lds) != hipSuccess ||
       *per_cu < 1)
     *per_cu = 1;
   if (hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || *cus < 1) *cus = 1;
@@ -243,17 +270,19 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
                              wefq_plan* out) {
   if (!out || !segs || nseg <= 0) return plan_fail(WEFQ_EINVAL, "plan needs at least one segment and an output");
   *out = nullptr;
-  if (block != 256 && block != 512) return plan_fail(WEFQ_EINVAL, "block must be 256 or 512");
+  if (block != 256 && block != 512 && block != 768) return plan_fail(WEFQ_EINVAL, "block must be 256, 512 or 768");
   WorkList w;
   std::vector<int64_t> seg_tiles;
   std::vector<double> seg_cost;
   std::vector<int> seg_units;
   wefq_status st = describe_segments(nseg, segs, w, seg_tiles, seg_cost, seg_units);
   if (st != WEFQ_OK) return st;
+  if (block == 768 && !all_wide(w))
+    return plan_fail(WEFQ_EINVAL, "block 768 runs FP32 plans whose tile shapes all belong to the 12-wave kernel");
   const int mode = w.mode, device = w.device;
   const size_t lds = w.lds;
   if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
-  const void* k = persistent_kernel(mode);
+  const void* k = persistent_kernel(mode, block);
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
   int per_cu = 0, cus = 0;
@@ -384,7 +413,8 @@ wefq_status wefq_runner_create(int32_t device, int32_t precision, int32_t max_se
   *out = nullptr;
   if (precision != WEFQ_FP32 && precision != WEFQ_BF16X3 && precision != WEFQ_FP64)
     return plan_fail(WEFQ_EINVAL, "runner precision must be FP32, BF16X3 or FP64");
-  if (block != 256 && block != 512) return plan_fail(WEFQ_EINVAL, "block must be 256 or 512");
+  if (block != 256 && block != 512 && block != 768) return plan_fail(WEFQ_EINVAL, "block must be 256, 512 or 768");
+  if (block == 768 && precision != WEFQ_FP32) return plan_fail(WEFQ_EINVAL, "block 768 runs FP32 runners only");
   if (max_segments < 1 || max_segments >= (1 << 15) || max_items < 1)
     return plan_fail(WEFQ_EINVAL, "max_segments must be in [1, 32767] and max_items >= 1");
   if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EINVAL, "bad device ordinal");
@@ -411,7 +441,9 @@ wefq_status wefq_runner_create(int32_t device, int32_t precision, int32_t max_se
   if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || dev_lds <= 0)
     dev_lds = 65536;
   const int limit = std::min(dev_lds, 163840) - 512;
-  if (hipFuncSetAttribute(persistent_kernel(r->mode), hipFuncAttributeMaxDynamicSharedMemorySize, limit) != hipSuccess) {
+  // (a runner of 768 threads launches the 8-wave kernel of 512 for batches with other tile shapes)
+  if (hipFuncSetAttribute(persistent_kernel(r->mode, r->block), hipFuncAttributeMaxDynamicSharedMemorySize, limit) != hipSuccess ||
+      hipFuncSetAttribute(persistent_kernel(r->mode, 512), hipFuncAttributeMaxDynamicSharedMemorySize, limit) != hipSuccess) {
     runner_free(r);
     return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
   }
@@ -432,8 +464,9 @@ wefq_status wefq_runner_launch(wefq_runner r, int32_t nseg, const wefq_segment* 
   if (w.device != r->device) return plan_fail(WEFQ_EINVAL, "segments must use cores on the runner's device");
   if (w.mode != r->mode) return plan_fail(WEFQ_EINVAL, "segments must use the runner's precision");
   if (hipSetDevice(r->device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
+  const int block = (r->block == 768 && !all_wide(w)) ? 512 : r->block;
   int per_cu = 0, cus = 0;
-  residency(r->mode, r->block, w.lds, r->device, &per_cu, &cus);
+  residency(r->mode, block, w.lds, r->device, &per_cu, &cus);
   st = make_items(w, seg_tiles, seg_cost, seg_units, per_cu * cus);
   if (st != WEFQ_OK) return st;
   const int nitems = (int)w.codes.size();
@@ -452,14 +485,8 @@ wefq_status wefq_runner_launch(wefq_runner r, int32_t nseg, const wefq_segment* 
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    PlanParams pp{sl.d_segs, sl.d_items, nitems, sl.d_counter};
     const int grid = std::max(1, std::min(per_cu * cus, nitems));
-    switch (r->mode) {
-      case 0: hipLaunchKernelGGL(apply_persistent_kernel<0>, dim3(grid), dim3(r->block), w.lds, s, pp); break;
-      case 1: hipLaunchKernelGGL(apply_persistent_kernel<1>, dim3(grid), dim3(r->block), w.lds, s, pp); break;
-      default: hipLaunchKernelGGL(apply_persistent_kernel<2>, dim3(grid), dim3(r->block), w.lds, s, pp); break;
-    }
-    e = hipGetLastError();
+    e = launch_persistent(r->mode, block, grid, w.lds, s, PlanParams{sl.d_segs, sl.d_items, nitems, sl.d_counter});
   }
   // the slot is busy until everything enqueued above has run (also after a failed enqueue)
   const hipError_t er = hipEventRecord(sl.done, s);

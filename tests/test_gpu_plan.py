@@ -140,6 +140,64 @@ def test_plan_with_anisotropic_cores():
     aniso.close()
 
 
+def test_twelve_wave_plan_matches_single_segment_applies():
+    """Plans of 768 threads run the 12-wave persistent kernel: the default FP32 shapes of
+    K = 3, 4, 8, 12 and 16 are among its tile shapes; results stay bitwise those of the
+    standalone applies, over graph replays and a direct launch."""
+    segs = segments("fp32", MIX)
+    refs = [c.apply_Q(f).clone() for c, f, _ in segs]
+    plan = wefq.Plan(segs, precision="fp32", block=768)
+    assert plan.info["block"] == 768 and plan.info["work_items"] > 0
+    for replay in range(3):
+        for _, _, q in segs:
+            q.fill_(float("nan"))
+        plan.launch()
+        torch.cuda.synchronize()
+        for (c, f, q), r in zip(segs, refs):
+            assert torch.equal(q, r), f"replay {replay} K={c.K}"
+        torch.ones(1000, device=dev()).sum().item()
+    for _, _, q in segs:
+        q.zero_()
+    plan.launch(graph=False)
+    torch.cuda.synchronize()
+    for (c, f, q), r in zip(segs, refs):
+        assert torch.equal(q, r)
+    plan.close()
+
+
+def test_twelve_wave_plan_refuses_other_shapes_and_precisions():
+    """768 threads take FP32 plans of the 12-wave kernel's tile shapes only (EINVAL before any
+    allocation or launch otherwise)."""
+    other = segments("fp32", [("hs", 10, None, 20)])                   # 6x6 quadrants
+    with pytest.raises(wefq.WefqError) as err:
+        wefq.Plan(other, precision="fp32", block=768)
+    assert err.value.status == _lib.WEFQ_EINVAL
+    c, f, q = segments("fp32", [("hs", 4, None, 20)])[0]
+    with pytest.raises(wefq.WefqError):
+        wefq.Plan([(c, f, q, 4)], precision="fp32", block=768)         # 4-cell tiles of 3x3
+    with pytest.raises(wefq.WefqError):
+        wefq.Plan(segments("fp64", [("hs", 4, None, 20)]), precision="fp64", block=768)
+    with pytest.raises(wefq.WefqError):
+        wefq.Runner(0, "fp64", block=768)
+
+
+def test_twelve_wave_runner_falls_back_for_other_shapes():
+    """A runner of 768 threads launches the 12-wave kernel for batches of its tile shapes and
+    the 8-wave kernel of 512 threads for the others; both bitwise equal to standalone applies."""
+    segs = segments("fp32", MIX[:4] + [("hs", 10, None, 21)])
+    refs = [c.apply_Q(f).clone() for c, f, _ in segs]
+    run = wefq.Runner(0, "fp32", max_segments=64, max_items=1 << 16, block=768)
+    stream = torch.cuda.current_stream(dev())
+    for pick in (range(4), range(5), range(4)):
+        for i in pick:
+            segs[i][2].fill_(float("nan"))
+        run.launch([segs[i] for i in pick], stream=stream)
+        torch.cuda.synchronize()
+        for i in pick:
+            assert torch.equal(segs[i][2], refs[i]), (list(pick), i)
+    run.close()
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_runner_launches_match_single_segment_applies(prec):
     """wefq_runner_launch: one persistent launch per call over a changing mix of segments,
@@ -181,7 +239,7 @@ def test_plan_autotuner_times_whole_plans_and_keeps_results():
     segs = segments("fp32", [("hs", 4, None, 64), ("vhs", 8, 0.5, 40), ("hs", 12, None, 33)])
     refs = [c.apply_Q(f).clone() for c, f, _ in segs]
     slots, block, tried = autotune.tune_plan(segs, "fp32", reps=2)
-    assert block in (256, 512) and len(slots) == len(segs)
+    assert block in (256, 512, 768) and len(slots) == len(segs)
     assert "block=512 slots=0,0,0" in tried and np.isfinite(min(tried.values()))
     plan = wefq.Plan([(c, f, q, s) for (c, f, q), s in zip(segs, slots)], precision="fp32", block=block)
     plan.launch()
