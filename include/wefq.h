@@ -286,7 +286,8 @@ typedef struct {
  * 8-wave kernel, every tile shape), or 768 (the 12-wave kernel, three waves per SIMD: FP32
  * plans whose segments all have quadrants up to 5x5 or 7x7 with one output state per MFMA
  * column group, or 9x9 with two, the default FP32 shapes of K = 0..9, 12 and 16; EINVAL
- * otherwise). */
+ * otherwise).  BF16X3 and FP64 plans whose segments all have their precision's default tile
+ * shapes run an 8-wave build of those shapes only, which spills fewer registers. */
 wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t block, void* stream,
                              wefq_plan* out);
 /* Replay the captured graph on stream (asynchronous).  Concurrent launches of one

@@ -50,17 +50,33 @@ __global__ void plan_reset_kernel(int* counter) {
     break;
 #define WEFQ_TILE_CASES_H(H_) WEFQ_TILE_CASE(H_, 1, 1) WEFQ_TILE_CASE(H_, 2, 1) WEFQ_TILE_CASE(H_, 4, 1)
 
-// Tile shapes of the 12-wave persistent kernel (768 threads, three waves per SIMD, 168
-// registers): FP32 quadrants up to 5x5 and 7x7 with one output state per column group, and 9x9
-// with two and the 17th radial row (the default FP32 shapes of K = 0..9, 12 and 16).  One kernel
-// body holding these shapes compiles without register spill; adding 6x6 spilled 32 bytes per
-// lane, adding 7x7 and 8x8 with two output states 100.
+// Builds of the persistent kernel (VARIANT):
+//  * kAll: 8 waves (256 or 512 threads), every tile shape.  One body holding them all spills
+//    registers in BF16x3 (148 bytes per lane) and FP64 (572);
+//  * kWide: 12 waves (768 threads, three per SIMD, 168 registers), FP32 quadrants up to 5x5
+//    and 7x7 with one output state per column group and 9x9 with two and the 17th radial row
+//    (the default FP32 shapes of K = 0..9, 12 and 16).  These compile together without spill;
+//    adding 6x6 spilled 32 bytes per lane, adding 7x7 and 8x8 with two output states 100;
+//  * kDefaults: 8 waves, the BF16x3 or FP64 shapes the core build picks by default on this
+//    device (BF16x3: 1x1 to 7x7 with one output state per column group, 7x7 to 9x9 with two,
+//    no spill; FP64: 1x1 to 5x5 with one, 6x6 and 7x7 with two, 7x7 to 9x9 with four, 300
+//    bytes).  Plans of these shapes measured 4-6% faster than with kAll.
+enum { kAll = 0, kWide = 1, kDefaults = 2 };
+
 __host__ __device__ constexpr bool wide_plan_shape(int H, int SLOTS, int RT) {
   return (SLOTS == 1 && RT == 1 && (H <= 5 || H == 7)) || (H == 9 && SLOTS == 2 && RT == 2);
 }
+__host__ __device__ constexpr bool default_plan_shape(int mode, int H, int SLOTS, int RT) {
+  return mode == 1 ? (SLOTS == 1 && RT == 1 && H <= 7) ||
+                         (SLOTS == 2 && ((RT == 1 && (H == 7 || H == 8)) || (RT == 2 && H == 9)))
+         : mode == 2 ? (SLOTS == 1 && RT == 1 && H <= 5) || (SLOTS == 2 && RT == 1 && (H == 6 || H == 7)) ||
+                           (SLOTS == 4 && ((RT == 1 && (H == 7 || H == 8)) || (RT == 2 && H == 9)))
+                     : false;
+}
 
-template <int MODE, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void apply_persistent_kernel(PlanParams pp) {
+template <int MODE, int VARIANT>
+__global__ __launch_bounds__(VARIANT == kWide ? 768 : 512) void apply_persistent_kernel(PlanParams pp) {
+  constexpr int WAVES = VARIANT == kWide ? 12 : 8;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int unit_ctr;
   __shared__ int item_sh;
@@ -74,10 +90,24 @@ __global__ __launch_bounds__(64 * WAVES) void apply_persistent_kernel(PlanParams
     const SegDesc& sd = pp.segs[(int)(code >> 48)];
     const int split = (int)((code >> 40) & 0xff);
     const int64_t tile = code & ((1LL << 40) - 1);
-    if constexpr (WAVES == 12) {
+    if constexpr (VARIANT == kWide) {
       switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
         WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
         WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(7, 1, 1) WEFQ_TILE_CASE(9, 2, 2)
+        default: break;
+      }
+    } else if constexpr (VARIANT == kDefaults && MODE == 1) {
+      switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
+        WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
+        WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(6, 1, 1) WEFQ_TILE_CASE(7, 1, 1) WEFQ_TILE_CASE(7, 2, 1)
+        WEFQ_TILE_CASE(8, 2, 1) WEFQ_TILE_CASE(9, 2, 2)
+        default: break;
+      }
+    } else if constexpr (VARIANT == kDefaults) {
+      switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
+        WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
+        WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(6, 2, 1) WEFQ_TILE_CASE(7, 2, 1) WEFQ_TILE_CASE(7, 4, 1)
+        WEFQ_TILE_CASE(8, 4, 1) WEFQ_TILE_CASE(9, 4, 2)
         default: break;
       }
     } else {
@@ -102,6 +132,7 @@ struct wefq_plan_s {
   int device = 0;
   int mode = 0;
   int block = 512;
+  int variant = kAll;
   int grid = 0;
   size_t lds = 0;
   int nitems = 0;
@@ -128,17 +159,19 @@ static void plan_free(wefq_plan_s* p) {
   delete p;
 }
 
-// Kernel of a plan precision (mode 0 FP32, 1 BF16X3, 2 FP64) and block size (768 threads: the
-// 12-wave FP32 kernel).
-static const void* persistent_kernel(int mode, int block) {
-  if (block == 768) return (const void*)apply_persistent_kernel<0, 12>;
-  return mode == 0 ? (const void*)apply_persistent_kernel<0, 8>
-         : mode == 1 ? (const void*)apply_persistent_kernel<1, 8> : (const void*)apply_persistent_kernel<2, 8>;
+// Kernel of a plan precision (mode 0 FP32, 1 BF16X3, 2 FP64) and build (kWide: FP32 only).
+static const void* persistent_kernel(int mode, int variant) {
+  if (variant == kWide) return (const void*)apply_persistent_kernel<0, kWide>;
+  if (variant == kDefaults && mode == 1) return (const void*)apply_persistent_kernel<1, kDefaults>;
+  if (variant == kDefaults && mode == 2) return (const void*)apply_persistent_kernel<2, kDefaults>;
+  return mode == 0 ? (const void*)apply_persistent_kernel<0, kAll>
+         : mode == 1 ? (const void*)apply_persistent_kernel<1, kAll> : (const void*)apply_persistent_kernel<2, kAll>;
 }
 
-static hipError_t launch_persistent(int mode, int block, int grid, size_t lds, hipStream_t s, PlanParams pp) {
+static hipError_t launch_persistent(int mode, int variant, int block, int grid, size_t lds, hipStream_t s,
+                                    PlanParams pp) {
   void* args[] = {&pp};
-  hipError_t e = hipLaunchKernel(persistent_kernel(mode, block), dim3(grid), dim3(block), args, lds, s);
+  hipError_t e = hipLaunchKernel(persistent_kernel(mode, variant), dim3(grid), dim3(block), args, lds, s);
   return e != hipSuccess ? e : hipGetLastError();
 }
 
@@ -146,7 +179,8 @@ static hipError_t plan_enqueue(const wefq_plan_s* p, hipStream_t s) {
   hipLaunchKernelGGL(plan_reset_kernel, dim3(1), dim3(64), 0, s, p->d_counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_persistent(p->mode, p->block, p->grid, p->lds, s, PlanParams{p->d_segs, p->d_items, p->nitems, p->d_counter});
+  return launch_persistent(p->mode, p->variant, p->block, p->grid, p->lds, s,
+                           PlanParams{p->d_segs, p->d_items, p->nitems, p->d_counter});
 }
 
 // A batch of segments made into a work list: the per-segment parameters and the item codes,
@@ -165,6 +199,15 @@ static bool all_wide(const WorkList& w) {
   for (const SegDesc& d : w.descs)
     if (!wide_plan_shape(d.H, d.SLOTS, d.RT)) return false;
   return true;
+}
+
+// The build of the persistent kernel for a work list at a block size (768 needs all_wide).
+static int kernel_variant(const WorkList& w, int block) {
+  if (block == 768) return kWide;
+  if (w.mode == 0) return kAll;
+  for (const SegDesc& d : w.descs)
+    if (!default_plan_shape(w.mode, d.H, d.SLOTS, d.RT)) return kAll;
+  return kDefaults;
 }
 
 // Validate the segments and build their descriptors (any mix of cores of one precision on one
@@ -253,12 +296,12 @@ static wefq_status make_items(WorkList& w, const std::vector<int64_t>& seg_tiles
   return WEFQ_OK;
 }
 
-// Workgroups of the persistent kernel resident per compute unit at (block, lds), and the
+// Workgroups of a persistent kernel build resident per compute unit at (block, lds), and the
 // compute unit count of the current device.
-static void residency(int mode, int block, size_t lds, int device, int* per_cu, int* cus) {
+static void residency(int mode, int variant, int block, size_t lds, int device, int* per_cu, int* cus) {
   *per_cu = 0;
   *cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, persistent_kernel(mode, block), block, lds) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, persistent_kernel(mode, variant), block, lds) != hipSuccess ||
       *per_cu < 1)
     *per_cu = 1;
   if (hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || *cus < 1) *cus = 1;
@@ -282,18 +325,20 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
   const int mode = w.mode, device = w.device;
   const size_t lds = w.lds;
   if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
-  const void* k = persistent_kernel(mode, block);
+  const int variant = kernel_variant(w, block);
+  const void* k = persistent_kernel(mode, variant);
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
   int per_cu = 0, cus = 0;
-  residency(mode, block, lds, device, &per_cu, &cus);
+  residency(mode, variant, block, lds, device, &per_cu, &cus);
   st = make_items(w, seg_tiles, seg_cost, seg_units, per_cu * cus);
   if (st != WEFQ_OK) return st;
   const std::vector<SegDesc>& descs = w.descs;
   const std::vector<int64_t>& codes = w.codes;
   wefq_plan_s* pl = new (std::nothrow) wefq_plan_s();
   if (!pl) return plan_fail(WEFQ_ENOMEM, "host allocation failed");
-  pl->device = device; pl->mode = mode; pl->block = block; pl->lds = lds; pl->nitems = (int)codes.size();
+  pl->device = device; pl->mode = mode; pl->block = block; pl->variant = variant; pl->lds = lds;
+  pl->nitems = (int)codes.size();
   bool ok = hipMalloc(&pl->d_segs, sizeof(SegDesc) * nseg) == hipSuccess &&
             hipMalloc(&pl->d_items, sizeof(int64_t) * std::max<size_t>(1, codes.size())) == hipSuccess &&
             hipMalloc(&pl->d_counter, sizeof(int) * 64) == hipSuccess;
@@ -441,9 +486,14 @@ wefq_status wefq_runner_create(int32_t device, int32_t precision, int32_t max_se
   if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || dev_lds <= 0)
     dev_lds = 65536;
   const int limit = std::min(dev_lds, 163840) - 512;
-  // (a runner of 768 threads launches the 8-wave kernel of 512 for batches with other tile shapes)
-  if (hipFuncSetAttribute(persistent_kernel(r->mode, r->block), hipFuncAttributeMaxDynamicSharedMemorySize, limit) != hipSuccess ||
-      hipFuncSetAttribute(persistent_kernel(r->mode, 512), hipFuncAttributeMaxDynamicSharedMemorySize, limit) != hipSuccess) {
+  // (every build a launch may pick: a runner of 768 threads launches the 8-wave kernel of 512
+  // for batches with other tile shapes)
+  bool lds_ok = true;
+  for (const int v : {kAll, kDefaults, kWide})
+    if (v != kWide || r->block == 768)
+      lds_ok = lds_ok && hipFuncSetAttribute(persistent_kernel(r->mode, v), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             limit) == hipSuccess;
+  if (!lds_ok) {
     runner_free(r);
     return plan_fail(WEFQ_EHIP, "cannot reserve LDS for the persistent kernel");
   }
@@ -465,8 +515,9 @@ wefq_status wefq_runner_launch(wefq_runner r, int32_t nseg, const wefq_segment* 
   if (w.mode != r->mode) return plan_fail(WEFQ_EINVAL, "segments must use the runner's precision");
   if (hipSetDevice(r->device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
   const int block = (r->block == 768 && !all_wide(w)) ? 512 : r->block;
+  const int variant = kernel_variant(w, block);
   int per_cu = 0, cus = 0;
-  residency(r->mode, block, w.lds, r->device, &per_cu, &cus);
+  residency(r->mode, variant, block, w.lds, r->device, &per_cu, &cus);
   st = make_items(w, seg_tiles, seg_cost, seg_units, per_cu * cus);
   if (st != WEFQ_OK) return st;
   const int nitems = (int)w.codes.size();
@@ -486,7 +537,8 @@ wefq_status wefq_runner_launch(wefq_runner r, int32_t nseg, const wefq_segment* 
   }
   if (e == hipSuccess) {
     const int grid = std::max(1, std::min(per_cu * cus, nitems));
-    e = launch_persistent(r->mode, block, grid, w.lds, s, PlanParams{sl.d_segs, sl.d_items, nitems, sl.d_counter});
+    e = launch_persistent(r->mode, variant, block, grid, w.lds, s,
+                          PlanParams{sl.d_segs, sl.d_items, nitems, sl.d_counter});
   }
   // the slot is busy until everything enqueued above has run (also after a failed enqueue)
   const hipError_t er = hipEventRecord(sl.done, s);
