@@ -87,10 +87,13 @@ def test_plan_tiles_without_pad_rows_match_padded_standalone_tiles(prec, slots):
     plan.close()
 
 
-def test_plan_tile_shape_override_keeps_results():
-    segs = segments("fp32", [("hs", 4, None, 40), ("vhs", 8, 0.5, 23)])
-    refs = [c.apply_Q(f).clone() for c, f, _ in segs]
-    plan = wefq.Plan([(c, f, q, 4) for c, f, q in segs], precision="fp32", block=256)
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_plan_tile_shape_override_keeps_results(prec):
+    """Non-default tile shapes (4-cell tiles): in BF16x3 and FP64 they take the build of the
+    persistent kernel that holds every shape, not the default-shape one."""
+    segs = segments(prec, [("hs", 4, None, 40), ("vhs", 8, 0.5, 23)])
+    refs = [c.apply_Q(f, precision=prec).clone() for c, f, _ in segs]
+    plan = wefq.Plan([(c, f, q, 4) for c, f, q in segs], precision=prec, block=256)
     plan.launch()
     torch.cuda.synchronize()
     for (_, _, q), r in zip(segs, refs):
