@@ -283,10 +283,11 @@ typedef struct {
  * reset and the kernel are captured once in a HIP graph.  Per-cell results equal
  * those of wefq_apply_Q bitwise.  Buffers and cores must outlive the plan; the plan
  * owns a small device work list.  Synchronizes stream.  block: 256 or 512 threads (the
- * 8-wave kernel, every tile shape), or 768 (the 12-wave kernel, three waves per SIMD: FP32
- * plans whose segments all have quadrants up to 5x5 or 7x7 with one output state per MFMA
- * column group, or 9x9 with two, the default FP32 shapes of K = 0..9, 12 and 16; EINVAL
- * otherwise).  BF16X3 and FP64 plans whose segments all have their precision's default tile
+ * 8-wave kernel, every tile shape), or 768 (a 12-wave kernel, three waves per SIMD, for FP32
+ * plans whose segments all have the shapes of one of its two builds: quadrants up to 5x5 or
+ * 7x7 with one output state per MFMA column group or 9x9 with two, the default FP32 shapes of
+ * K = 0..9, 12 and 16; or 6x6 with one and 7x7 or 8x8 with two, those of K = 10, 11 and
+ * 13..15.  EINVAL otherwise).  BF16X3 and FP64 plans whose segments all have their precision's default tile
  * shapes run an 8-wave build of those shapes only, which spills fewer registers. */
 wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t block, void* stream,
                              wefq_plan* out);

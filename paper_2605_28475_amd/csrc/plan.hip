@@ -57,14 +57,19 @@ __global__ void plan_reset_kernel(int* counter) {
 //    and 7x7 with one output state per column group and 9x9 with two and the 17th radial row
 //    (the default FP32 shapes of K = 0..9, 12 and 16).  These compile together without spill;
 //    adding 6x6 spilled 32 bytes per lane, adding 7x7 and 8x8 with two output states 100;
+//  * kWide2: 12 waves, FP32 quadrants 6x6 with one output state per column group and 7x7 and
+//    8x8 with two (the default shapes of K = 10, 11 and 13 to 15), 8 bytes of spill per lane;
 //  * kDefaults: 8 waves, the BF16x3 or FP64 shapes the core build picks by default on this
 //    device (BF16x3: 1x1 to 7x7 with one output state per column group, 7x7 to 9x9 with two,
 //    no spill; FP64: 1x1 to 5x5 with one, 6x6 and 7x7 with two, 7x7 to 9x9 with four, 300
 //    bytes).  Plans of these shapes measured 4-6% faster than with kAll.
-enum { kAll = 0, kWide = 1, kDefaults = 2 };
+enum { kAll = 0, kWide = 1, kDefaults = 2, kWide2 = 3 };
 
 __host__ __device__ constexpr bool wide_plan_shape(int H, int SLOTS, int RT) {
   return (SLOTS == 1 && RT == 1 && (H <= 5 || H == 7)) || (H == 9 && SLOTS == 2 && RT == 2);
+}
+__host__ __device__ constexpr bool wide2_plan_shape(int H, int SLOTS, int RT) {
+  return RT == 1 && ((SLOTS == 1 && H == 6) || (SLOTS == 2 && (H == 7 || H == 8)));
 }
 __host__ __device__ constexpr bool default_plan_shape(int mode, int H, int SLOTS, int RT) {
   return mode == 1 ? (SLOTS == 1 && RT == 1 && H <= 7) ||
@@ -75,8 +80,9 @@ __host__ __device__ constexpr bool default_plan_shape(int mode, int H, int SLOTS
 }
 
 template <int MODE, int VARIANT>
-__global__ __launch_bounds__(VARIANT == kWide ? 768 : 512) void apply_persistent_kernel(PlanParams pp) {
-  constexpr int WAVES = VARIANT == kWide ? 12 : 8;
+__global__ __launch_bounds__(VARIANT == kWide || VARIANT == kWide2 ? 768 : 512) void apply_persistent_kernel(
+    PlanParams pp) {
+  constexpr int WAVES = VARIANT == kWide || VARIANT == kWide2 ? 12 : 8;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   __shared__ int unit_ctr;
   __shared__ int item_sh;
@@ -94,6 +100,11 @@ __global__ __launch_bounds__(VARIANT == kWide ? 768 : 512) void apply_persistent
       switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
         WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
         WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(7, 1, 1) WEFQ_TILE_CASE(9, 2, 2)
+        default: break;
+      }
+    } else if constexpr (VARIANT == kWide2) {
+      switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
+        WEFQ_TILE_CASE(6, 1, 1) WEFQ_TILE_CASE(7, 2, 1) WEFQ_TILE_CASE(8, 2, 1)
         default: break;
       }
     } else if constexpr (VARIANT == kDefaults && MODE == 1) {
@@ -162,6 +173,7 @@ static void plan_free(wefq_plan_s* p) {
 // Kernel of a plan precision (mode 0 FP32, 1 BF16X3, 2 FP64) and build (kWide: FP32 only).
 static const void* persistent_kernel(int mode, int variant) {
   if (variant == kWide) return (const void*)apply_persistent_kernel<0, kWide>;
+  if (variant == kWide2) return (const void*)apply_persistent_kernel<0, kWide2>;
   if (variant == kDefaults && mode == 1) return (const void*)apply_persistent_kernel<1, kDefaults>;
   if (variant == kDefaults && mode == 2) return (const void*)apply_persistent_kernel<2, kDefaults>;
   return mode == 0 ? (const void*)apply_persistent_kernel<0, kAll>
@@ -193,17 +205,22 @@ struct WorkList {
   std::vector<int64_t> codes;
 };
 
-// Whether every segment of an FP32 work list has a tile shape of the 12-wave kernel.
-static bool all_wide(const WorkList& w) {
-  if (w.mode != 0) return false;
-  for (const SegDesc& d : w.descs)
-    if (!wide_plan_shape(d.H, d.SLOTS, d.RT)) return false;
-  return true;
+// The 12-wave build whose tile shapes cover every segment of an FP32 work list, or kAll when
+// none does.
+static int wide_variant(const WorkList& w) {
+  if (w.mode != 0) return kAll;
+  bool a = true, b = true;
+  for (const SegDesc& d : w.descs) {
+    a = a && wide_plan_shape(d.H, d.SLOTS, d.RT);
+    b = b && wide2_plan_shape(d.H, d.SLOTS, d.RT);
+  }
+  return a ? kWide : (b ? kWide2 : kAll);
 }
+static bool all_wide(const WorkList& w) { return wide_variant(w) != kAll; }
 
 // The build of the persistent kernel for a work list at a block size (768 needs all_wide).
 static int kernel_variant(const WorkList& w, int block) {
-  if (block == 768) return kWide;
+  if (block == 768) return wide_variant(w);
   if (w.mode == 0) return kAll;
   for (const SegDesc& d : w.descs)
     if (!default_plan_shape(w.mode, d.H, d.SLOTS, d.RT)) return kAll;
@@ -321,7 +338,7 @@ wefq_status wefq_plan_create(int32_t nseg, const wefq_segment* segs, int32_t blo
   wefq_status st = describe_segments(nseg, segs, w, seg_tiles, seg_cost, seg_units);
   if (st != WEFQ_OK) return st;
   if (block == 768 && !all_wide(w))
-    return plan_fail(WEFQ_EINVAL, "block 768 runs FP32 plans whose tile shapes all belong to the 12-wave kernel");
+    return plan_fail(WEFQ_EINVAL, "block 768 runs FP32 plans whose tile shapes all belong to one 12-wave build");
   const int mode = w.mode, device = w.device;
   const size_t lds = w.lds;
   if (hipSetDevice(device) != hipSuccess) return plan_fail(WEFQ_EHIP, "hipSetDevice failed");
@@ -489,8 +506,8 @@ wefq_status wefq_runner_create(int32_t device, int32_t precision, int32_t max_se
   // (every build a launch may pick: a runner of 768 threads launches the 8-wave kernel of 512
   // for batches with other tile shapes)
   bool lds_ok = true;
-  for (const int v : {kAll, kDefaults, kWide})
-    if (v != kWide || r->block == 768)
+  for (const int v : {kAll, kDefaults, kWide, kWide2})
+    if ((v != kWide && v != kWide2) || r->block == 768)
       lds_ok = lds_ok && hipFuncSetAttribute(persistent_kernel(r->mode, v), hipFuncAttributeMaxDynamicSharedMemorySize,
                                              limit) == hipSuccess;
   if (!lds_ok) {

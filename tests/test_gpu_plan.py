@@ -168,10 +168,27 @@ def test_twelve_wave_plan_matches_single_segment_applies():
     plan.close()
 
 
+def test_second_twelve_wave_build_matches_single_segment_applies():
+    """The other 12-wave build: 6x6 quadrants (K = 10, 11) and 7x7 and 8x8 with two output
+    states (K = 13, 14, 15), bitwise equal to the standalone applies."""
+    segs = segments("fp32", [("hs", 10, None, 37), ("vhs", 11, 0.5, 16), ("hs", 13, None, 9),
+                             ("vhs", 14, 0.5, 12), ("hs", 15, None, 5)])
+    refs = [c.apply_Q(f).clone() for c, f, _ in segs]
+    plan = wefq.Plan(segs, precision="fp32", block=768)
+    for replay in range(2):
+        for _, _, q in segs:
+            q.fill_(float("nan"))
+        plan.launch()
+        torch.cuda.synchronize()
+        for (c, f, q), r in zip(segs, refs):
+            assert torch.equal(q, r), f"replay {replay} K={c.K}"
+    plan.close()
+
+
 def test_twelve_wave_plan_refuses_other_shapes_and_precisions():
-    """768 threads take FP32 plans of the 12-wave kernel's tile shapes only (EINVAL before any
-    allocation or launch otherwise)."""
-    other = segments("fp32", [("hs", 10, None, 20)])                   # 6x6 quadrants
+    """768 threads take FP32 plans whose tile shapes all belong to one 12-wave build (EINVAL
+    before any allocation or launch otherwise)."""
+    other = segments("fp32", [("hs", 10, None, 20), ("hs", 12, None, 20)])     # one shape of each build
     with pytest.raises(wefq.WefqError) as err:
         wefq.Plan(other, precision="fp32", block=768)
     assert err.value.status == _lib.WEFQ_EINVAL
@@ -185,13 +202,14 @@ def test_twelve_wave_plan_refuses_other_shapes_and_precisions():
 
 
 def test_twelve_wave_runner_falls_back_for_other_shapes():
-    """A runner of 768 threads launches the 12-wave kernel for batches of its tile shapes and
-    the 8-wave kernel of 512 threads for the others; both bitwise equal to standalone applies."""
+    """A runner of 768 threads launches a 12-wave build for batches whose tile shapes it covers
+    and the 8-wave kernel of 512 threads for the others; all bitwise equal to standalone
+    applies."""
     segs = segments("fp32", MIX[:4] + [("hs", 10, None, 21)])
     refs = [c.apply_Q(f).clone() for c, f, _ in segs]
     run = wefq.Runner(0, "fp32", max_segments=64, max_items=1 << 16, block=768)
     stream = torch.cuda.current_stream(dev())
-    for pick in (range(4), range(5), range(4)):
+    for pick in (range(4), range(5), [4], range(4)):
         for i in pick:
             segs[i][2].fill_(float("nan"))
         run.launch([segs[i] for i in pick], stream=stream)
