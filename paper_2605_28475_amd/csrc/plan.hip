@@ -65,18 +65,25 @@ __global__ void plan_reset_kernel(int* counter) {
 //    bytes).  Plans of these shapes measured 4-6% faster than with kAll.
 enum { kAll = 0, kWide = 1, kDefaults = 2, kWide2 = 3 };
 
+// The shape lists (H, SLOTS, RT) of the restricted builds; the kernel's switch and the host's
+// membership tests are both generated from them.
+#define WEFQ_WIDE_SHAPES(X) X(1, 1, 1) X(2, 1, 1) X(3, 1, 1) X(4, 1, 1) X(5, 1, 1) X(7, 1, 1) X(9, 2, 2)
+#define WEFQ_WIDE2_SHAPES(X) X(6, 1, 1) X(7, 2, 1) X(8, 2, 1)
+#define WEFQ_BF16_DEFAULT_SHAPES(X) \
+  X(1, 1, 1) X(2, 1, 1) X(3, 1, 1) X(4, 1, 1) X(5, 1, 1) X(6, 1, 1) X(7, 1, 1) X(7, 2, 1) X(8, 2, 1) X(9, 2, 2)
+#define WEFQ_FP64_DEFAULT_SHAPES(X) \
+  X(1, 1, 1) X(2, 1, 1) X(3, 1, 1) X(4, 1, 1) X(5, 1, 1) X(6, 2, 1) X(7, 2, 1) X(7, 4, 1) X(8, 4, 1) X(9, 4, 2)
+#define WEFQ_SHAPE_IS(H_, S_, R_) || (H == (H_) && SLOTS == (S_) && RT == (R_))
+
 __host__ __device__ constexpr bool wide_plan_shape(int H, int SLOTS, int RT) {
-  return (SLOTS == 1 && RT == 1 && (H <= 5 || H == 7)) || (H == 9 && SLOTS == 2 && RT == 2);
+  return false WEFQ_WIDE_SHAPES(WEFQ_SHAPE_IS);
 }
 __host__ __device__ constexpr bool wide2_plan_shape(int H, int SLOTS, int RT) {
-  return RT == 1 && ((SLOTS == 1 && H == 6) || (SLOTS == 2 && (H == 7 || H == 8)));
+  return false WEFQ_WIDE2_SHAPES(WEFQ_SHAPE_IS);
 }
 __host__ __device__ constexpr bool default_plan_shape(int mode, int H, int SLOTS, int RT) {
-  return mode == 1 ? (SLOTS == 1 && RT == 1 && H <= 7) ||
-                         (SLOTS == 2 && ((RT == 1 && (H == 7 || H == 8)) || (RT == 2 && H == 9)))
-         : mode == 2 ? (SLOTS == 1 && RT == 1 && H <= 5) || (SLOTS == 2 && RT == 1 && (H == 6 || H == 7)) ||
-                           (SLOTS == 4 && ((RT == 1 && (H == 7 || H == 8)) || (RT == 2 && H == 9)))
-                     : false;
+  return mode == 1 ? (false WEFQ_BF16_DEFAULT_SHAPES(WEFQ_SHAPE_IS))
+                   : mode == 2 ? (false WEFQ_FP64_DEFAULT_SHAPES(WEFQ_SHAPE_IS)) : false;
 }
 
 template <int MODE, int VARIANT>
@@ -98,27 +105,22 @@ __global__ __launch_bounds__(VARIANT == kWide || VARIANT == kWide2 ? 768 : 512) 
     const int64_t tile = code & ((1LL << 40) - 1);
     if constexpr (VARIANT == kWide) {
       switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
-        WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
-        WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(7, 1, 1) WEFQ_TILE_CASE(9, 2, 2)
+        WEFQ_WIDE_SHAPES(WEFQ_TILE_CASE)
         default: break;
       }
     } else if constexpr (VARIANT == kWide2) {
       switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
-        WEFQ_TILE_CASE(6, 1, 1) WEFQ_TILE_CASE(7, 2, 1) WEFQ_TILE_CASE(8, 2, 1)
+        WEFQ_WIDE2_SHAPES(WEFQ_TILE_CASE)
         default: break;
       }
     } else if constexpr (VARIANT == kDefaults && MODE == 1) {
       switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
-        WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
-        WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(6, 1, 1) WEFQ_TILE_CASE(7, 1, 1) WEFQ_TILE_CASE(7, 2, 1)
-        WEFQ_TILE_CASE(8, 2, 1) WEFQ_TILE_CASE(9, 2, 2)
+        WEFQ_BF16_DEFAULT_SHAPES(WEFQ_TILE_CASE)
         default: break;
       }
     } else if constexpr (VARIANT == kDefaults) {
       switch (sd.H * 100 + sd.SLOTS * 10 + sd.RT) {
-        WEFQ_TILE_CASE(1, 1, 1) WEFQ_TILE_CASE(2, 1, 1) WEFQ_TILE_CASE(3, 1, 1) WEFQ_TILE_CASE(4, 1, 1)
-        WEFQ_TILE_CASE(5, 1, 1) WEFQ_TILE_CASE(6, 2, 1) WEFQ_TILE_CASE(7, 2, 1) WEFQ_TILE_CASE(7, 4, 1)
-        WEFQ_TILE_CASE(8, 4, 1) WEFQ_TILE_CASE(9, 4, 2)
+        WEFQ_FP64_DEFAULT_SHAPES(WEFQ_TILE_CASE)
         default: break;
       }
     } else {
