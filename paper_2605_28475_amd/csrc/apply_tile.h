@@ -77,11 +77,14 @@ __device__ __forceinline__ void outer_product(T* phi, const T* u, const T* w) {
 // lane 168 registers: the 12-wave instances hoist the R tile only up to 6x6 quadrants) or 16
 // (four per SIMD, 128 registers; quadrants up to 5x5).
 // PAD_ALL: the tile layout's pad rows in tiles of every width (false: 16-cell tiles only).
+// AHEAD: FP32 tiles whose R tile streams load each batch of it one batch ahead of its MFMAs
+// (the persistent plan kernel: 2% faster there; the standalone kernel at K = L = 12 ran 12%
+// slower with it).
 // TWO: two inputs f, g; the coupling is symmetric, sum w (f_x (x) g_y + g_x (x) f_y), or with
 // ANTI antisymmetric, sum w (f_x (x) g_y - g_x (x) f_y), contracted with the tiles the caller
 // passes as the A operand, and the result combined as out = (out + result) / 2.
 template <int H, int SLOTS, int RT, int MODE, bool TWO = false, bool ANTI = false, int WAVES = 8,
-          bool PAD_ALL = true>
+          bool PAD_ALL = true, bool AHEAD = false>
 __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int split, unsigned char* lds_raw,
                                           int* unit_ctr_p) {
   typedef typename ModeTraits<MODE>::T T;
@@ -505,6 +508,27 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
 #pragma unroll
           for (int t = 0; t < HH; ++t)
             acc[gi] = __builtin_amdgcn_mfma_f64_16x16x4f64(a64[t], phi[t], acc[gi], 0, 0, 0);
+        } else if constexpr (MODE == 0 && AHEAD) {
+          // the streamed R tile, 8 steps per batch, the next batch's loads issued ahead of the
+          // current batch's MFMAs
+          const v4f* At = reinterpret_cast<const v4f*>(p.Rt32) + (int64_t)ct * Q4 * 64 + lane;
+          v4f x0 = At[0];
+          v4f x1 = (4 < HH) ? At[64] : (v4f){0, 0, 0, 0};
+#pragma unroll
+          for (int t0 = 0; t0 < HH; t0 += 8) {
+            v4f n0 = (v4f){0, 0, 0, 0}, n1 = (v4f){0, 0, 0, 0};
+            if (t0 + 8 < HH) n0 = At[((t0 + 8) / 4) * 64];
+            if (t0 + 12 < HH) n1 = At[((t0 + 8) / 4 + 1) * 64];
+            float av[8];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) { av[t] = x0[t]; av[t + 4] = x1[t]; }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+              if (t0 + t < HH) acc[gi] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], phi[t0 + t], acc[gi], 0, 0, 0);
+            x0 = n0;
+            x1 = n1;
+          }
         } else if constexpr (MODE == 0) {
           const v4f* At = reinterpret_cast<const v4f*>(p.Rt32) + (int64_t)ct * Q4 * 64 + lane;
 #pragma unroll
@@ -536,8 +560,20 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
               if (t0 + t < HH) acc[gi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], phi[t0 + t], acc[gi], 0, 0, 0);
           }
         } else {
+          // the streamed hi/lo R tiles, the next step's loads issued ahead of the current
+          // step's MFMAs (against loads in the step: K = L = 12 with 65,536 cells 32.3 -> 31.6 ms,
+          // K = L = 14 with 16,384 cells 23.2 -> 22.1 ms, K = L = 10 1.5% slower)
+          const int64_t off0 = ((int64_t)ct * U * 64 + lane) * 8;
+          v8bf ahn = HOIST ? ahi[0] : *reinterpret_cast<const v8bf*>(p.Rhi + off0);
+          v8bf aln = HOIST ? alo[0] : *reinterpret_cast<const v8bf*>(p.Rlo + off0);
 #pragma unroll
           for (int uu8 = 0; uu8 < U; ++uu8) {
+            const v8bf ah = ahn, al = aln;
+            if (uu8 + 1 < U) {
+              const int64_t offn = off0 + (int64_t)(uu8 + 1) * 64 * 8;
+              ahn = HOIST ? ahi[HOIST ? uu8 + 1 : 0] : *reinterpret_cast<const v8bf*>(p.Rhi + offn);
+              aln = HOIST ? alo[HOIST ? uu8 + 1 : 0] : *reinterpret_cast<const v8bf*>(p.Rlo + offn);
+            }
             // split hi/lo two values at a time: one packed round-to-nearest conversion gives
             // both hi halves, which are unpacked back to FP32 by a shift and a mask
             v8bf bh, bl;
@@ -552,9 +588,6 @@ __device__ __forceinline__ void mfma_tile(const MfmaParams& p, int64_t tile, int
               bh[e] = h[0]; bh[e + 1] = h[1];
               bl[e] = l[0]; bl[e + 1] = l[1];
             }
-            const int64_t off = (((int64_t)ct * U + uu8) * 64 + lane) * 8;
-            const v8bf ah = HOIST ? ahi[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rhi + off);
-            const v8bf al = HOIST ? alo[HOIST ? uu8 : 0] : *reinterpret_cast<const v8bf*>(p.Rlo + off);
             acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[gi], 0, 0, 0);
             acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[gi], 0, 0, 0);
             acc[gi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[gi], 0, 0, 0);

@@ -44,9 +44,9 @@ __global__ void plan_reset_kernel(int* counter) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
-#define WEFQ_TILE_CASE(H_, S_, R_)                                                                 \
-  case (H_) * 100 + (S_) * 10 + (R_):                                                              \
-    mfma_tile<H_, S_, R_, MODE, false, false, WAVES, false>(sd.p, tile, split, lds_raw, &unit_ctr); \
+#define WEFQ_TILE_CASE(H_, S_, R_)                                                                        \
+  case (H_) * 100 + (S_) * 10 + (R_):                                                                     \
+    mfma_tile<H_, S_, R_, MODE, false, false, WAVES, false, true>(sd.p, tile, split, lds_raw, &unit_ctr); \
     break;
 #define WEFQ_TILE_CASES_H(H_) WEFQ_TILE_CASE(H_, 1, 1) WEFQ_TILE_CASE(H_, 2, 1) WEFQ_TILE_CASE(H_, 4, 1)
 
