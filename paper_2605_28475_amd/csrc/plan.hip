@@ -52,7 +52,7 @@ __global__ void plan_reset_kernel(int* counter) {
 
 // Builds of the persistent kernel (VARIANT):
 //  * kAll: 8 waves (256 or 512 threads), every tile shape.  One body holding them all spills
-//    registers in BF16x3 (148 bytes per lane) and FP64 (572);
+//    registers in BF16x3 (8 bytes per lane) and FP64 (572);
 //  * kWide: 12 waves (768 threads, three per SIMD, 168 registers), FP32 quadrants up to 5x5
 //    and 7x7 with one output state per column group and 9x9 with two and the 17th radial row
 //    (the default FP32 shapes of K = 0..9, 12 and 16).  These compile together without spill;
